@@ -1,0 +1,314 @@
+#!/usr/bin/env python3
+"""Benchmark of the multidimensional complex FFT on one MI355X.
+
+Headline step: one 512^3 complex64 forward transform followed by its inverse
+(the paper times forward + inverse and reports half, Section 5), inputs
+already resident in HBM.  value = GFLOP/s by the 5 N log2 N count per
+transform.  Beside it: per-pass kernel times (HIP events on the launch
+stream) for the roofline of the dominant kernel, the 16-bit storage, batched,
+2D/1D and Poisson forward+backward variants, and the FP64 CPU oracle timed on
+the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
+PAPER_512_FP32_GFLOPS = 18.9e3   # CS-2, 512x512 PEs, 959 us (paper, Table 1 and Section 5.3)
+METRIC = "512^3 c2c 3D FFT µs, GFLOP/s, % HBM roofline; FP16/batched/fwd+bwd vs FP32"
+
+
+def flops(N: int) -> float:
+    return 5.0 * N * math.log2(N) if N > 1 else 0.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_events(fn, steps: int, warmup: int):
+    """Per-call milliseconds of fn() over `steps` calls, HIP events on the
+    current stream (the stream the library launches on)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    total = ev[0].elapsed_time(ev[-1])
+    return total / steps, per
+
+
+def bench_plan_passes(plan, x, y, steps, warmup):
+    """Average kernel duration of each pass alone (ms)."""
+    out = []
+    for i in range(plan.num_passes):
+        ms, per = time_events(lambda i=i: plan.execute_pass(i, x, y, 0), steps, warmup)
+        out.append({"pass": i, "ms": ms, "ms_min": min(per)})
+    return out
+
+
+def headline(ws, torch, steps, warmup):
+    import synth
+    n = 512
+    N = n ** 3
+    log("headline: generating 512^3 complex64 N(0,1) seed 1")
+    a = synth.normal_c64((n, n, n), seed=1)
+    x = torch.from_numpy(a).cuda()
+    del a
+    y = torch.empty_like(x)
+    r = torch.empty_like(x)
+    plan = ws.Plan(n, n, n, "c64", -1)
+
+    def step():
+        plan.execute(x, y)
+        plan.execute_inverse(y, r)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_step, per = time_events(step, steps, warmup)
+    wall = time.perf_counter() - t0
+    fwd_ms, _ = time_events(lambda: plan.execute(x, y), steps, warmup)
+    passes = bench_plan_passes(plan, x, y, steps, warmup)
+    bytes_per_pass = 2 * N * 8
+    for p in passes:
+        p["GBps"] = bytes_per_pass / (p["ms"] * 1e-3) / 1e9
+        p["hbm_frac"] = p["GBps"] * 1e9 / HBM_PEAK
+    res = {
+        "plan": plan.describe(),
+        "ms_per_step": ms_step,
+        "ms_step_min": min(per),
+        "ms_step_median": statistics.median(per),
+        "spread_pct": 100.0 * (max(per) - min(per)) / statistics.median(per),
+        "us_per_transform": ms_step * 1e3 / 2,
+        "us_forward": fwd_ms * 1e3,
+        "passes": passes,
+        "wall_s": wall,
+    }
+    del x, y, r
+    torch.cuda.empty_cache()
+    return res, plan
+
+
+def variant_c16(ws, torch, kind, steps, warmup, flags=0):
+    import synth
+    n = 512
+    N = n ** 3
+    log(f"variant {kind}: generating 512^3 0.5*N(0,1) rounded to {kind}")
+    z = synth.normal_c64((n, n, n), seed=2)
+    z *= 0.5
+    if kind == "fp16":
+        pairs = z.view(np.float32).reshape(n, n, n, 2).astype(np.float16)
+        x = torch.from_numpy(pairs).cuda()
+    else:
+        xf = torch.from_numpy(z.view(np.float32).reshape(n, n, n, 2)).cuda()
+        x = xf.to(torch.bfloat16)    # nearest-even, as the storage rounding
+        del xf
+    del z
+    y = torch.empty_like(x)
+    r = torch.empty_like(x)
+    plan = ws.Plan(n, n, n, kind, -1, flags)
+    ms, _ = time_events(lambda: (plan.execute(x, y), plan.execute_inverse(y, r)), steps, warmup)
+    passes = bench_plan_passes(plan, x, y, steps, warmup)
+    del x, y, r
+    torch.cuda.empty_cache()
+    us = ms * 1e3 / 2
+    return {"us_per_transform": us, "GFLOPs": flops(N) / (us * 1e-6) / 1e9,
+            "hbm_frac": 3 * 2 * N * 4 / (us * 1e-6) / HBM_PEAK,
+            "pass_ms": [p["ms"] for p in passes], "S": plan.scale_log2}
+
+
+def variant_batched(ws, torch, steps, warmup):
+    import synth
+    shapes = synth.batched_shapes(96, seed=3)
+    log("variant batched: 96 uneven arrays")
+    xs, ys, plans = [], [], []
+    for i, (nx, ny, nz) in enumerate(shapes):
+        g = np.random.default_rng([3, i])
+        a = (g.uniform(-1, 1, (nz, ny, nx)) + 1j * g.uniform(-1, 1, (nz, ny, nx))).astype(np.complex64)
+        xs.append(torch.from_numpy(a).cuda())
+        ys.append(torch.empty_like(xs[-1]))
+        plans.append(ws.Plan(nx, ny, nz, "c64", -1))
+    tot = sum(nx * ny * nz for nx, ny, nz in shapes)
+    fl = sum(flops(nx * ny * nz) for nx, ny, nz in shapes)
+    ms, _ = time_events(lambda: ws.execute_batched(plans, xs, ys), steps, warmup)
+    ms_loop, _ = time_events(lambda: [p.execute(a, b) for p, a, b in zip(plans, xs, ys)], steps, warmup)
+    byts = sum(2 * 8 * nx * ny * nz * sum(d > 1 for d in (nx, ny, nz)) for nx, ny, nz in shapes)
+    del xs, ys
+    torch.cuda.empty_cache()
+    return {"arrays": len(shapes), "elements": tot, "GiB_in_plus_out": 2 * 8 * tot / 2 ** 30,
+            "ms_batched": ms, "ms_loop_of_plans": ms_loop, "GFLOPs": fl / (ms * 1e-3) / 1e9,
+            "hbm_frac": byts / (ms * 1e-3) / HBM_PEAK}
+
+
+def variant_rank(ws, torch, shape, steps, warmup, batch=1):
+    import synth
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    log(f"variant {shape} x{batch}")
+    a = synth.normal_c64((batch * nz, ny, nx), seed=1)
+    x = torch.from_numpy(a).cuda()
+    del a
+    y = torch.empty_like(x)
+    plan = ws.Plan(nx, ny, nz, "c64", -1)
+    if batch == 1:
+        ms, _ = time_events(lambda: plan.execute(x, y), steps, warmup)
+    else:
+        xv, yv = list(x.view(batch, -1)), list(y.view(batch, -1))
+        ms, _ = time_events(lambda: ws.execute_batched([plan] * batch, xv, yv), steps, warmup)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"plan": plan.describe(), "ms": ms, "GFLOPs": batch * flops(N) / (ms * 1e-3) / 1e9,
+            "passes": plan.num_passes,
+            "hbm_frac_min_passes": batch * 2 * 2 * N * 8 / (ms * 1e-3) / HBM_PEAK}
+
+
+def variant_poisson(ws, torch, steps, warmup):
+    import synth
+    n = 256
+    log("variant poisson 256^3: bumps")
+    f = torch.from_numpy(synth.gaussian_bumps(n, 64, 0.05, seed=4).astype(np.float32)).cuda()
+    w = torch.from_numpy(synth.poisson_weights(n, seed=4).astype(np.float32)).cuda()
+
+    def fwd():
+        return (ws.poisson_solve(f) * w).sum()
+
+    def fwd_bwd():
+        fg = f.detach().requires_grad_(True)
+        loss = (ws.poisson_solve(fg) * w).sum()
+        loss.backward()
+        return fg.grad
+
+    with torch.no_grad():
+        ms_f, _ = time_events(fwd, steps, warmup)
+    ms_fb, _ = time_events(fwd_bwd, steps, warmup)
+    plan = ws.get_plan(torch.empty((n, n, n), dtype=torch.complex64, device="cuda"), -1)
+    x = torch.empty((n, n, n), dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    ms_fft, _ = time_events(lambda: plan.execute(x, y), steps, warmup)
+    return {"ms_forward": ms_f, "ms_forward_backward": ms_fb, "ms_plain_fft_256": ms_fft,
+            "ffts_forward": 2, "ffts_forward_backward": 4}
+
+
+def cpu_baseline():
+    import oracle
+    import synth
+    n = 512
+    N = n ** 3
+    threads = oracle.default_threads()
+    a = synth.normal_c64((n, n, n), seed=1).astype(np.complex128)
+    t0 = time.perf_counter()
+    X = oracle.fftn(a, -1, threads)
+    t1 = time.perf_counter()
+    oracle.fftn(X, +1, threads)
+    t2 = time.perf_counter()
+    secs = (t2 - t0) / 2
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": flops(N) / secs / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"one 512^3 forward+inverse round trip (the headline step), FP64 C oracle, "
+                      f"{threads} threads; {secs * 1e3:.0f} ms per transform (fwd {(t1 - t0):.2f} s); "
+                      f"cpu: {cpu}"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+    import torch
+    from paper_2209_15040_amd import binding as ws
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+
+    K, W = args.steps, args.warmup
+    head, plan = headline(ws, torch, K, W)
+    n = 512
+    N = n ** 3
+    us = head["us_per_transform"]
+    value = flops(N) / (us * 1e-6) / 1e9
+    dom = max(head["passes"], key=lambda p: p["ms"])
+    algo_bytes = 2 * N * 8
+    roofline = {"bound": "hbm", "achieved": algo_bytes / (dom["ms"] * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": algo_bytes / (dom["ms"] * 1e-3) / HBM_PEAK, "traffic": None,
+                "kernel": f"pass {dom['pass']} of {head['plan']}",
+                "algorithmic_bytes_per_launch": algo_bytes}
+    variants = {}
+    if not args.no_variants:
+        vs = max(5, K // 2)
+        variants["fp16"] = variant_c16(ws, torch, "fp16", vs, 2)
+        variants["bf16"] = variant_c16(ws, torch, "bf16", vs, 2)
+        variants["bf16_fp32_twiddles"] = variant_c16(ws, torch, "bf16", vs, 2, ws.FLAG_FP32_TWIDDLES)
+        variants["batched_96"] = variant_batched(ws, torch, vs, 2)
+        variants["2d_8192"] = variant_rank(ws, torch, (8192, 8192, 1), vs, 2)
+        variants["1d_65536_x1024"] = variant_rank(ws, torch, (65536, 1, 1), vs, 2, batch=1024)
+        variants["32cubed"] = variant_rank(ws, torch, (32, 32, 32), vs, 2)
+        variants["poisson_256"] = variant_poisson(ws, torch, vs, 2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: FP64 oracle, 512^3 round trip")
+        cpu = cpu_baseline()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": value / PAPER_512_FP32_GFLOPS,
+        "baseline_note": "paper: 959 us = 18.9 TFLOP/s on a Cerebras CS-2 (512x512 PEs, FP32); context only",
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^3 complex64 3D c2c FFT, forward + inverse per step, N(0,1) seed 1",
+                   "shape": [n, n, n], "storage": "complex64", "transforms_per_step": 2},
+        "us_per_transform": us,
+        "us_forward": head["us_forward"],
+        "hbm_frac_3_passes": 3 * algo_bytes / (us * 1e-6) / HBM_PEAK,
+        "step_spread_pct": head["spread_pct"],
+        "passes": head["passes"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,166 @@
+/*
+ * wsfft: multidimensional complex-to-complex FFT for AMD Instinct MI355X
+ * (gfx950), computed as one batched pencil pass ("superstep") per axis with
+ * the data redistribution between supersteps done by the passes' own
+ * addressing.
+ *
+ * The problem (paper, Section 1 and Section 2.2): for an nx x ny x nz array a,
+ *
+ *   X[kx,ky,kz] = sum_{x,y,z} a[x,y,z] exp(sign * 2*pi*i * (kx*x/nx + ky*y/ny + kz*z/nz))
+ *
+ * computed as 1D DFTs along x, then y, then z (the order does not change the
+ * exact result).  sign = -1 is the forward transform.  The inverse of
+ * Section 4.2 conjugates the roots of unity and scales by 1/N; here that is
+ * wsfft_execute_inverse (or wsfft_execute_adjoint plus a 1/N scale).
+ *
+ * Layout: dense, interleaved complex, x fastest: element (x, y, z) sits at
+ * linear index x + nx*(y + ny*z) -- a contiguous torch tensor of shape
+ * (nz, ny, nx).  2D arrays use nz = 1, 1D arrays ny = nz = 1.  Storage types:
+ *   WSFFT_C64       FP32 re, FP32 im (8 bytes, 8-byte aligned)
+ *   WSFFT_C16_FP16  FP16 re, FP16 im (4 bytes, 4-byte aligned)
+ *   WSFFT_C16_BF16  BF16 re, BF16 im (4 bytes, 4-byte aligned)
+ * All arithmetic is FP32 (the paper measures FP32 and FP16; Section 4.1 and
+ * Section 5).  Twiddle factors are evaluated in FP64 on the host and rounded
+ * to nearest even: to the storage type for the 16-bit types, to FP32 for
+ * WSFFT_C64 or when WSFFT_FLAG_FP32_TWIDDLES is given.
+ *
+ * Reduced precision: each pass p of a 16-bit plan multiplies its output by
+ * 2^-s_p with s_p = ceil(log2(n_p) / 2), so the stored result is
+ * 2^-S * DFT(a) with S = sum of s_p (wsfft_plan_scale_log2).  WSFFT_C64 plans
+ * have S = 0.
+ *
+ * Errors: every call validates its arguments before touching the device and
+ * returns a status; wsfft_plan_create* return NULL and record the status for
+ * wsfft_get_last_error() (thread-local).  Execution calls only enqueue work on
+ * the given stream (0 = the null stream): they never allocate, copy from the
+ * host or synchronise, so they can be captured in a HIP graph.  Device-side
+ * faults surface at the caller's next synchronisation, as in HIP.
+ *
+ * Ownership: the caller owns `in` and `out` (device pointers on the device
+ * that was current when the plan was created) and keeps them alive until the
+ * stream work completes.  A plan owns its twiddle tables and, for axes longer
+ * than one pass can hold, its work buffer.  Plans are immutable after
+ * creation, so one plan may run concurrently on several streams -- except
+ * plans with a work buffer (wsfft_plan_work_bytes > 0), which must not run
+ * concurrently with themselves.  `in == out` is allowed, except for a plan
+ * with exactly one split axis (wsfft_plan_num_passes larger than the number
+ * of axes of length > 1 and wsfft_plan_work_bytes == 0), whose first pass must
+ * read a buffer it does not write: such calls return WSFFT_ERROR_INVALID_VALUE.
+ * Otherwise `in` and `out` must not overlap, and `in` is never written.
+ */
+#ifndef WSFFT_H
+#define WSFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wsfft_plan_s* wsfft_plan_t;
+
+typedef enum {
+    WSFFT_C64 = 0,
+    WSFFT_C16_FP16 = 1,
+    WSFFT_C16_BF16 = 2
+} wsfft_dtype_t;
+
+typedef enum {
+    WSFFT_SUCCESS = 0,
+    WSFFT_ERROR_INVALID_VALUE = 1,    /* a size < 1, sign not +-1, unknown dtype or flag, count < 0 */
+    WSFFT_ERROR_UNSUPPORTED_SIZE = 2, /* an axis with a prime factor other than 2 or 3, or too large */
+    WSFFT_ERROR_NULL_POINTER = 3,
+    WSFFT_ERROR_MISALIGNED = 4,       /* a pointer not aligned to its element size */
+    WSFFT_ERROR_OUT_OF_MEMORY = 5,
+    WSFFT_ERROR_NO_DEVICE = 6,        /* no visible HIP device */
+    WSFFT_ERROR_HIP = 7,              /* a HIP runtime call failed (e.g. a launch) */
+    WSFFT_ERROR_INVALID_PLAN = 8,     /* NULL, destroyed, or created on another device */
+    WSFFT_ERROR_WRONG_DEVICE = 9      /* current device differs from the plan's */
+} wsfft_status_t;
+
+/* Plan flags for wsfft_plan_create_ex. */
+#define WSFFT_FLAG_FP32_TWIDDLES 1u   /* 16-bit plans: keep twiddles in FP32 */
+
+/*
+ * Create a plan for an nx x ny x nz transform of the given storage type with
+ * kernel sign `sign` (-1 forward, +1 backward).  Every axis length must be
+ * of the form 2^a 3^b and at most WSFFT_MAX_AXIS (2^20); an axis longer than
+ * one pass holds (16384 unit-stride, 1024 strided) must split into two
+ * factors of at most 1024.  The whole array holds at most 2^40 elements and
+ * each pass at most 2^32 - 1 work-items.  Builds the twiddle tables (one per
+ * distinct pass length) in FP64 on the host, rounds them and copies them to
+ * the current device.
+ * Returns NULL on error (see wsfft_get_last_error).
+ */
+#define WSFFT_MAX_AXIS 1048576
+wsfft_plan_t wsfft_plan_create(int64_t nx, int64_t ny, int64_t nz, wsfft_dtype_t dtype, int sign);
+wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtype_t dtype, int sign,
+                                  unsigned flags);
+
+/* Status of the last wsfft_plan_create* call on this thread. */
+wsfft_status_t wsfft_get_last_error(void);
+
+/* out = 2^-S * sum with the plan's sign (unnormalised).  The superstep
+ * sequence of Section 1: one pass per axis of length > 1. */
+wsfft_status_t wsfft_execute(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream);
+
+/* out = 2^-S * sum with the opposite sign, unnormalised: the adjoint (conjugate
+ * transpose) of wsfft_execute for C64 plans.  Section 4.2's inverse reverses
+ * the steps with conjugated roots. */
+wsfft_status_t wsfft_execute_adjoint(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream);
+
+/* out = 2^-S / N * sum with the opposite sign: the inverse of wsfft_execute
+ * (Section 4.2), with the 1/N folded into the last pass. */
+wsfft_status_t wsfft_execute_inverse(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream);
+
+/*
+ * `count` independent transforms in one call: transform i runs plans[i] from
+ * in[i] to out[i] (adjoint != 0 selects wsfft_execute_adjoint semantics).
+ * Plans may differ in shape; they must share dtype and device.  The work is
+ * issued pass by pass: all arrays' first passes in one launch, then all
+ * second passes, then all third (fewer launches when shapes allow), so the
+ * whole batch is a handful of launches that a HIP graph can capture.  The
+ * same plan may appear several times (e.g. one plan over many pencils);
+ * plans with a work buffer may not.  When every entry uses the same plan and
+ * both in[i] and out[i] advance by exactly one array per entry, each pass is
+ * a single launch over the whole batch.  Validation covers every entry
+ * before any work is enqueued.
+ */
+wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const void* const* in,
+                                     void* const* out, int adjoint, hipStream_t stream);
+
+/* Enqueue only pass `index` (0-based, < wsfft_plan_num_passes) of the
+ * transform wsfft_execute (mode 0), wsfft_execute_adjoint (1) or
+ * wsfft_execute_inverse (2) would run, with the same buffers.  Running every
+ * index in order equals the full call; one index alone is for per-pass timing
+ * and profiling. */
+wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const void* in, void* out,
+                                  hipStream_t stream);
+
+/* S of the stored 2^-S scaling (0 for WSFFT_C64); -1 for an invalid plan. */
+int wsfft_plan_scale_log2(wsfft_plan_t plan);
+
+/* Number of HBM passes one execute makes; -1 for an invalid plan. */
+int wsfft_plan_num_passes(wsfft_plan_t plan);
+
+/* Bytes of plan-owned device work buffer (0 unless an axis needs two passes
+ * and cannot run in place); -1 for an invalid plan. */
+int64_t wsfft_plan_work_bytes(wsfft_plan_t plan);
+
+/* Writes a one-line, NUL-terminated description of the pass schedule into
+ * buf (at most len bytes).  Returns the status. */
+wsfft_status_t wsfft_plan_describe(wsfft_plan_t plan, char* buf, size_t len);
+
+/* Synchronises the plan's device, then frees the plan.  NULL is ignored. */
+void wsfft_plan_destroy(wsfft_plan_t plan);
+
+/* Static string for a status code. */
+const char* wsfft_status_string(wsfft_status_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSFFT_H */

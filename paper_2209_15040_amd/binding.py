@@ -1,0 +1,331 @@
+"""Python binding of libwsfft: the MI355X multidimensional complex FFT.
+
+Argument marshalling only -- every step of a transform runs in the HIP
+kernels of ``libwsfft.so`` (built by ``python -m paper_2209_15040_amd.build``).
+PyTorch supplies device memory and streams.  There is no CPU fallback: if the
+library is missing, importing this package raises.
+
+Tensor conventions (x fastest, as the C-ABI):
+
+* complex64 tensors of shape (nz, ny, nx), (ny, nx) or (nx,);
+* 16-bit storage as float16 / bfloat16 tensors with a trailing dimension of
+  2 holding (re, im): shape (nz, ny, nx, 2) etc.
+
+The names follow the C-ABI (``include/wsfft.h``): :class:`Plan` wraps
+``wsfft_plan_create`` and its ``execute`` / ``execute_adjoint`` /
+``execute_inverse``; :func:`execute_batched` wraps ``wsfft_execute_batched``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwsfft.so")
+
+C64, C16_FP16, C16_BF16 = 0, 1, 2
+FLAG_FP32_TWIDDLES = 1
+DTYPES = {"c64": C64, "fp16": C16_FP16, "bf16": C16_BF16}
+_TORCH_DTYPE = {C64: torch.complex64, C16_FP16: torch.float16, C16_BF16: torch.bfloat16}
+
+STATUS = {
+    0: "success", 1: "invalid value", 2: "unsupported size", 3: "null pointer",
+    4: "misaligned pointer", 5: "out of device memory", 6: "no HIP device",
+    7: "HIP runtime error", 8: "invalid plan", 9: "wrong device",
+}
+
+
+class WsfftError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"wsfft {what}: {STATUS.get(status, status)} ({status})")
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2209_15040_amd.build` "
+                      "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i64, _int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+
+
+def _sig(name, restype, argtypes):
+    fn = getattr(_lib, name)
+    fn.restype = restype
+    fn.argtypes = argtypes
+    return fn
+
+
+_plan_create_ex = _sig("wsfft_plan_create_ex", _vp, [_i64, _i64, _i64, _int, _int, ctypes.c_uint])
+_get_last_error = _sig("wsfft_get_last_error", _int, [])
+_execute = _sig("wsfft_execute", _int, [_vp, _vp, _vp, _vp])
+_execute_adjoint = _sig("wsfft_execute_adjoint", _int, [_vp, _vp, _vp, _vp])
+_execute_inverse = _sig("wsfft_execute_inverse", _int, [_vp, _vp, _vp, _vp])
+_execute_batched = _sig("wsfft_execute_batched", _int,
+                        [_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _int, _vp])
+_execute_pass = _sig("wsfft_execute_pass", _int, [_vp, _int, _int, _vp, _vp, _vp])
+_scale_log2 = _sig("wsfft_plan_scale_log2", _int, [_vp])
+_num_passes = _sig("wsfft_plan_num_passes", _int, [_vp])
+_work_bytes = _sig("wsfft_plan_work_bytes", _i64, [_vp])
+_describe = _sig("wsfft_plan_describe", _int, [_vp, ctypes.c_char_p, ctypes.c_size_t])
+_destroy = _sig("wsfft_plan_destroy", None, [_vp])
+_real_to_complex = _sig("wsfft_real_to_complex", _int, [_vp, _vp, _i64, _vp])
+_complex_real_part = _sig("wsfft_complex_real_part", _int, [_vp, _vp, _i64, _vp])
+_poisson_symbol = _sig("wsfft_poisson_symbol", _int, [_vp, _i64, _i64, _i64, _vp])
+
+
+def _check(st: int, what: str) -> None:
+    if st != 0:
+        raise WsfftError(st, what)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def shape_xyz(shape, dtype: int):
+    """(nx, ny, nz) of a tensor shape in the binding's conventions."""
+    s = tuple(shape)
+    if dtype != C64:
+        if not s or s[-1] != 2:
+            raise ValueError("16-bit storage needs a trailing (re, im) dimension of 2")
+        s = s[:-1]
+    if len(s) == 1:
+        return s[0], 1, 1
+    if len(s) == 2:
+        return s[1], s[0], 1
+    if len(s) == 3:
+        return s[2], s[1], s[0]
+    raise ValueError("rank 1..3 only")
+
+
+class Plan:
+    """A wsfft plan for an nx x ny x nz transform (``wsfft_plan_create_ex``)."""
+
+    def __init__(self, nx: int, ny: int = 1, nz: int = 1, dtype="c64", sign: int = -1, flags: int = 0):
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        self.nx, self.ny, self.nz, self.sign, self.flags = int(nx), int(ny), int(nz), int(sign), int(flags)
+        self.device = torch.cuda.current_device()
+        h = _plan_create_ex(self.nx, self.ny, self.nz, self.dtype, self.sign, self.flags)
+        if not h:
+            raise WsfftError(_get_last_error(), f"plan_create({nx},{ny},{nz})")
+        self._h = h
+
+    @classmethod
+    def for_tensor(cls, x: torch.Tensor, sign: int = -1, flags: int = 0) -> "Plan":
+        dt = {torch.complex64: C64, torch.float16: C16_FP16, torch.bfloat16: C16_BF16}[x.dtype]
+        return cls(*shape_xyz(x.shape, dt), dtype=dt, sign=sign, flags=flags)
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    @property
+    def size(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def scale_log2(self) -> int:
+        return _scale_log2(self._h)
+
+    @property
+    def num_passes(self) -> int:
+        return _num_passes(self._h)
+
+    @property
+    def work_bytes(self) -> int:
+        return _work_bytes(self._h)
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        _check(_describe(self._h, buf, len(buf)), "plan_describe")
+        return buf.value.decode()
+
+    def _check_tensor(self, t: torch.Tensor, name: str) -> None:
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != _TORCH_DTYPE[self.dtype]:
+            raise TypeError(f"{name} has dtype {t.dtype}, plan wants {_TORCH_DTYPE[self.dtype]}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        per = 1 if self.dtype == C64 else 2
+        if t.numel() != self.size * per:
+            raise ValueError(f"{name} has {t.numel()} elements, plan wants {self.size * per}")
+
+    def _run(self, fn, x, out, stream, what):
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        _check(fn(self._h, x.data_ptr(), out.data_ptr(), _stream(stream)), what)
+        return out
+
+    def execute(self, x, out=None, stream=None):
+        """out = 2^-S * DFT with the plan's sign (unnormalised)."""
+        return self._run(_execute, x, out, stream, "execute")
+
+    def execute_adjoint(self, x, out=None, stream=None):
+        """out = 2^-S * DFT with the opposite sign (unnormalised)."""
+        return self._run(_execute_adjoint, x, out, stream, "execute_adjoint")
+
+    def execute_inverse(self, x, out=None, stream=None):
+        """out = 2^-S / N * DFT with the opposite sign."""
+        return self._run(_execute_inverse, x, out, stream, "execute_inverse")
+
+    def execute_pass(self, index: int, x, out, mode: int = 0, stream=None):
+        """Only pass `index` of execute (mode 0) / adjoint (1) / inverse (2)."""
+        self._check_tensor(x, "input")
+        self._check_tensor(out, "output")
+        _check(_execute_pass(self._h, int(index), int(mode), x.data_ptr(), out.data_ptr(), _stream(stream)),
+               "execute_pass")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def execute_batched(plans, ins, outs, adjoint: bool = False, stream=None) -> None:
+    """``wsfft_execute_batched`` over lists of plans and tensors."""
+    n = len(plans)
+    if len(ins) != n or len(outs) != n:
+        raise ValueError("plans, ins and outs must have one entry each")
+    for p, i, o in zip(plans, ins, outs):
+        p._check_tensor(i, "input")
+        p._check_tensor(o, "output")
+    arr = ctypes.c_void_p * max(n, 1)
+    ph = arr(*[p.handle for p in plans])
+    ip = arr(*[t.data_ptr() for t in ins])
+    op = arr(*[t.data_ptr() for t in outs])
+    _check(_execute_batched(n, ph, ip, op, int(bool(adjoint)), _stream(stream)), "execute_batched")
+
+
+# ---- plan cache and functional forms ------------------------------------------------
+
+_cache: dict = {}
+_cache_mu = threading.Lock()
+
+
+def get_plan(x: torch.Tensor, sign: int = -1, flags: int = 0) -> Plan:
+    dt = {torch.complex64: C64, torch.float16: C16_FP16, torch.bfloat16: C16_BF16}[x.dtype]
+    key = (shape_xyz(x.shape, dt), dt, sign, flags, x.device.index)
+    with _cache_mu:
+        p = _cache.get(key)
+        if p is None:
+            with torch.cuda.device(x.device):
+                p = Plan(*key[0], dtype=dt, sign=sign, flags=flags)
+            _cache[key] = p
+        return p
+
+
+def fftn(x: torch.Tensor, sign: int = -1) -> torch.Tensor:
+    """Unnormalised DFT over every axis of x (2^-S scaled for 16-bit storage)."""
+    return get_plan(x, sign).execute(x)
+
+
+def ifftn(x: torch.Tensor) -> torch.Tensor:
+    """Normalised inverse of :func:`fftn` (1/N and the opposite sign)."""
+    return get_plan(x, -1).execute_inverse(x)
+
+
+# ---- autograd ------------------------------------------------------------------------
+# PyTorch's convention for a C-linear map y = A x: grad_x = A^H grad_y.
+
+class FFTn(torch.autograd.Function):
+    """y = unnormalised DFT with kernel sign `sign`; backward = adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, x, sign: int = -1):
+        ctx.sign = sign
+        return get_plan(x, sign).execute(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return get_plan(g, ctx.sign).execute_adjoint(g.contiguous()), None
+
+
+class IFFTn(torch.autograd.Function):
+    """y = (1/N) DFT with kernel sign -sign; backward = (1/N) DFT with sign `sign`."""
+
+    @staticmethod
+    def forward(ctx, x, sign: int = -1):
+        ctx.sign = sign
+        return get_plan(x, sign).execute_inverse(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return get_plan(g, -ctx.sign).execute_inverse(g.contiguous()), None
+
+
+def _real_to_complex_run(x: torch.Tensor) -> torch.Tensor:
+    out = torch.empty(x.shape, dtype=torch.complex64, device=x.device)
+    _check(_real_to_complex(x.data_ptr(), out.data_ptr(), x.numel(), _stream(None)), "real_to_complex")
+    return out
+
+
+def _complex_real_run(z: torch.Tensor) -> torch.Tensor:
+    out = torch.empty(z.shape, dtype=torch.float32, device=z.device)
+    _check(_complex_real_part(z.data_ptr(), out.data_ptr(), z.numel(), _stream(None)), "complex_real_part")
+    return out
+
+
+class RealToComplex(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x):
+        if x.dtype != torch.float32 or not x.is_cuda:
+            raise TypeError("RealToComplex takes a float32 device tensor")
+        return _real_to_complex_run(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return _complex_real_run(g.contiguous())
+
+
+class ComplexRealPart(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, z):
+        if z.dtype != torch.complex64 or not z.is_cuda:
+            raise TypeError("ComplexRealPart takes a complex64 device tensor")
+        return _complex_real_run(z.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return _real_to_complex_run(g.contiguous())
+
+
+class PoissonSymbol(torch.autograd.Function):
+    """X(k) -> -X(k)/|k|^2, k = 0 -> 0 (real multiplier: self-adjoint)."""
+
+    @staticmethod
+    def forward(ctx, z):
+        if z.dtype != torch.complex64 or not z.is_cuda or z.dim() != 3:
+            raise TypeError("PoissonSymbol takes a (nz, ny, nx) complex64 device tensor")
+        out = z.contiguous().clone()
+        nz, ny, nx = out.shape
+        _check(_poisson_symbol(out.data_ptr(), nx, ny, nz, _stream(None)), "poisson_symbol")
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        return PoissonSymbol.forward(ctx, g)
+
+
+def poisson_solve(f: torch.Tensor) -> torch.Tensor:
+    """u = Re(IFFT(-FFT(f)/|k|^2)) on the periodic box [0, 2*pi)^3, differentiable."""
+    z = RealToComplex.apply(f)
+    F = FFTn.apply(z, -1)
+    U = PoissonSymbol.apply(F)
+    u = IFFTn.apply(U, -1)
+    return ComplexRealPart.apply(u)

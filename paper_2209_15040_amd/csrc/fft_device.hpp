@@ -1,0 +1,456 @@
+// Device side of the pencil FFT passes for gfx950 (CDNA4, wave64).
+//
+// One pass = one superstep of the multidimensional FFT (paper, Section 1 and
+// Section 2.2): a batch of independent 1D DFTs ("pencils") of length N along
+// one axis.  The redistribution between supersteps (paper, Section 4.3) is
+// done by addressing: a workgroup loads a tile of pencils straight from HBM
+// with coalesced row segments, transforms them through registers and LDS and
+// writes the results back to the same positions.
+//
+// Each 1D transform is a Stockham autosort Cooley-Tukey FFT (paper, Section
+// 4.1 describes the radix-2 form, which keeps the even and odd halves
+// contiguous so no bit reversal is needed).  Here the stages use radix 2, 3,
+// 4, 8 and 16.  Stage s with radix R and current sub-transform length Ns
+// takes butterfly b in [0, N/R):
+//   inputs  x[b + r*N/R], r in [0, R)
+//   twiddle x[b + r*N/R] *= W_(Ns*R)^((b mod Ns) * r)
+//   R-point DFT
+//   outputs y[(b div Ns)*Ns*R + (b mod Ns) + r*Ns]
+// The first stage's inputs and the last stage's outputs both sit at
+// b + r*N/R, so global loads and stores share one coalesced pattern.
+//
+// Complex products use fused multiply-adds (paper, Section 4.1 fuses the
+// four multiplies and two adds of a complex product into FMAC operations).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace wsfft {
+
+// ---------------------------------------------------------------- complex ---
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 w) {
+    return make_float2(fmaf(a.x, w.x, -a.y * w.y), fmaf(a.x, w.y, a.y * w.x));
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// a * (SIGN * i)
+template <int SIGN> __device__ __forceinline__ float2 crot90(float2 a) {
+    return SIGN < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// ------------------------------------------------------- small-radix DFTs ---
+// In-place R-point DFT of v[0..R) with kernel exp(SIGN * 2*pi*i*j*k/R).
+template <int R, int SIGN> struct Dft;
+
+template <int SIGN> struct Dft<2, SIGN> {
+    static __device__ __forceinline__ void run(float2* v) {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <int SIGN> struct Dft<3, SIGN> {
+    static __device__ __forceinline__ void run(float2* v) {
+        const float h = 0.86602540378443864676f;   // sin(2*pi/3)
+        const float2 t = cadd(v[1], v[2]);
+        const float2 d = csub(v[1], v[2]);
+        const float2 m = make_float2(fmaf(-0.5f, t.x, v[0].x), fmaf(-0.5f, t.y, v[0].y));
+        const float2 r = crot90<SIGN>(cscale(d, h));   // SIGN*i*sin(2pi/3)*d
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, r);
+        v[2] = csub(m, r);
+    }
+};
+
+template <int SIGN> struct Dft<4, SIGN> {
+    static __device__ __forceinline__ void run(float2* v) {
+        const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        const float2 t2 = cadd(v[1], v[3]), t3 = crot90<SIGN>(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    }
+};
+
+// 8 = 2 x 4: even/odd 4-point DFTs, odd part twiddled by W_8^k.
+template <int SIGN> struct Dft<8, SIGN> {
+    static __device__ __forceinline__ void run(float2* v) {
+        const float c = 0.70710678118654752440f;
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, SIGN>::run(e);
+        Dft<4, SIGN>::run(o);
+        // W_8^1 = c*(1 + SIGN*i), W_8^2 = SIGN*i, W_8^3 = c*(-1 + SIGN*i)
+        o[1] = SIGN < 0 ? make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x))
+                        : make_float2(c * (o[1].x - o[1].y), c * (o[1].y + o[1].x));
+        o[2] = crot90<SIGN>(o[2]);
+        o[3] = SIGN < 0 ? make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y))
+                        : make_float2(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 4] = csub(e[k], o[k]);
+        }
+    }
+};
+
+// 16 = 4 x 4: X[k1 + 4 k2] = sum_n2 W4^(n2 k2) W16^(n2 k1) sum_n1 a[4 n1 + n2] W4^(n1 k1)
+template <int SIGN> struct Dft<16, SIGN> {
+    static __device__ __forceinline__ void run(float2* v) {
+        // W16^m = (cos(2 pi m/16), SIGN*sin(2 pi m/16)) for the m that occur
+        const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+        const float c2 = 0.70710678118654752440f;
+        float2 y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            float2 t[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+            Dft<4, SIGN>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+        }
+        const float sg = (float)SIGN;
+        const float2 w1 = make_float2(c1, sg * s1);     // m = 1
+        const float2 w2 = make_float2(c2, sg * c2);     // m = 2
+        const float2 w3 = make_float2(s1, sg * c1);     // m = 3
+        const float2 w6 = make_float2(-c2, sg * c2);    // m = 6
+        const float2 w9 = make_float2(-c1, -sg * s1);   // m = 9
+        y[1][1] = cmul(y[1][1], w1);
+        y[1][2] = cmul(y[1][2], w2);
+        y[1][3] = cmul(y[1][3], w3);
+        y[2][1] = cmul(y[2][1], w2);
+        y[2][2] = crot90<SIGN>(y[2][2]);                // m = 4
+        y[2][3] = cmul(y[2][3], w6);
+        y[3][1] = cmul(y[3][1], w3);
+        y[3][2] = cmul(y[3][2], w6);
+        y[3][3] = cmul(y[3][3], w9);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            Dft<4, SIGN>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
+    }
+};
+
+// ------------------------------------------------------ stage schedule ---
+struct Radices {
+    int n;
+    int r[24];
+};
+
+// Radix schedule for a length N = 2^a 3^b: radix-3 stages first, then the
+// power of two in radix-8 stages, with one radix-16, radix-4 or radix-2 stage
+// to take up the remainder.
+constexpr Radices make_radices(int N) {
+    Radices R{0, {}};
+    int m = N;
+    while (m % 3 == 0) { R.r[R.n++] = 3; m /= 3; }
+    int e = 0;
+    while (m % 2 == 0) { ++e; m /= 2; }
+    int first = 0;
+    if (e % 3 == 1) first = (e >= 4) ? 16 : 2;
+    else if (e % 3 == 2) first = 4;
+    if (first == 16) e -= 4;
+    else if (first == 4) e -= 2;
+    else if (first == 2) e -= 1;
+    if (first) R.r[R.n++] = first;
+    while (e >= 3) { R.r[R.n++] = 8; e -= 3; }
+    return R;
+}
+
+constexpr int max_radix(const Radices& R) {
+    int m = 1;
+    for (int i = 0; i < R.n; ++i) m = R.r[i] > m ? R.r[i] : m;
+    return m;
+}
+
+constexpr int stage_ns(const Radices& R, int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= R.r[i];
+    return p;
+}
+
+// --------------------------------------------------------- storage types ---
+struct IoC64 {   // complex64: FP32 re, FP32 im
+    static constexpr int bytes = 8;
+    static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
+        return reinterpret_cast<const float2*>(p)[i];
+    }
+    static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
+        reinterpret_cast<float2*>(p)[i] = v;
+    }
+};
+
+struct IoF16 {   // FP16 re, FP16 im
+    static constexpr int bytes = 4;
+    static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
+        const __half2 h = reinterpret_cast<const __half2*>(p)[i];
+        return __half22float2(h);
+    }
+    static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
+        reinterpret_cast<__half2*>(p)[i] = __float22half2_rn(v);
+    }
+};
+
+// BF16 = top 16 bits of an FP32; storage rounds to nearest even.
+__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // quiet NaN
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
+    static constexpr int bytes = 4;
+    static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
+        const uint32_t w = reinterpret_cast<const uint32_t*>(p)[i];
+        return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+    }
+    static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
+        reinterpret_cast<uint32_t*>(p)[i] = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
+    }
+};
+
+// -------------------------------------------------------------- pass args ---
+// A pass transforms pencils of length N.  Two layouts:
+//   contiguous: pencil q in [0, C) has element e at q*os1_in + e (stride 1)
+//   strided:    pencil (c, o1, o2), c in [0, C) a unit-stride column index,
+//               element e at c + e*es_in + o1*os1_in + o2*os2_in
+// Outputs go to c*cs_out + e*es_out + o1*os1_out + o2*os2_out (strided) or
+// q*os1_out + e (contiguous).  The second set of strides lets the first pass
+// of a two-pass (four-step) axis write its results transposed.
+struct PassArgs {
+    const void* src;
+    void* dst;
+    const float2* tw;     // W_N^m = exp(-2*pi*i*m/N), m in [0, N)
+    const float2* tw4;    // four-step twiddles W_M^m, m in [0, M), or null
+    int64_t M;            // full axis length for tw4
+    int64_t C, O1, O2;
+    int64_t es_in, os1_in, os2_in;
+    int64_t es_out, cs_out, os1_out, os2_out;
+    int32_t tw4_mode;     // 0: none; 1: output e of column c times W_M^(c*e); 2: W_M^(o1*e)
+    int32_t tstore;       // strided layout only: store columns as contiguous runs via LDS
+    float scale;          // multiplies every stored value
+};
+
+// ------------------------------------------------------------ the kernel ---
+template <int N, int T, int P, bool STRIDED, class IO, int SIGN>
+struct PencilPass {
+    static constexpr Radices RD = make_radices(N);
+    static constexpr int NS = RD.n;
+    // LDS layout: strided tiles store [element][column], contiguous tiles
+    // [pencil][element]; one float2 of padding per row breaks power-of-two
+    // bank strides.
+    static constexpr int LDS_ROW = STRIDED ? (P + 1) : (N + 1);
+    static constexpr int LDS_ELEMS = STRIDED ? N * (P + 1) : P * (N + 1);
+    static constexpr int lds_bytes() { return LDS_ELEMS * 8; }
+    static constexpr int threads() { return T * P; }
+
+    template <int S> struct St {
+        static constexpr int R = RD.r[S];
+        static constexpr int Ns = stage_ns(RD, S);
+        static constexpr int NBF = N / R;               // butterflies
+        static constexpr int NB = (NBF + T - 1) / T;    // per thread
+        static constexpr int TWS = N / (Ns * R);        // twiddle table stride
+    };
+
+    static constexpr int maxv() {
+        int m = 1;
+        for (int s = 0; s < NS; ++s) {
+            const int R = RD.r[s];
+            const int nb = (N / R + T - 1) / T;
+            m = nb * R > m ? nb * R : m;
+        }
+        return m;
+    }
+
+    __device__ __forceinline__ static int lidx(int p, int e) {
+        return STRIDED ? e * LDS_ROW + p : p * LDS_ROW + e;
+    }
+
+    struct Ctx {
+        int p, j;
+        bool valid;
+        int64_t col;          // global column (strided) or pencil (contiguous)
+        int64_t o1;
+        int64_t base_in, base_out;
+    };
+
+    template <int S>
+    __device__ __forceinline__ static void butterflies(float2* v, int j, const float2* __restrict__ tw) {
+        using Q = St<S>;
+#pragma unroll
+        for (int t = 0; t < Q::NB; ++t) {
+            const int b = j + t * T;
+            if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+            float2* u = v + t * Q::R;
+            if (S > 0) {
+                const int k = b % Q::Ns;
+#pragma unroll
+                for (int r = 1; r < Q::R; ++r) {
+                    float2 w = tw[k * r * Q::TWS];
+                    if (SIGN > 0) w.y = -w.y;
+                    u[r] = cmul(u[r], w);
+                }
+            }
+            Dft<Q::R, SIGN>::run(u);
+        }
+    }
+
+    template <int S>
+    __device__ __forceinline__ static void write_lds(float2* lds, const float2* v, int p, int j) {
+        using Q = St<S>;
+#pragma unroll
+        for (int t = 0; t < Q::NB; ++t) {
+            const int b = j + t * T;
+            if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+            const int k = b % Q::Ns;
+            const int o = (b / Q::Ns) * Q::Ns * Q::R + k;
+#pragma unroll
+            for (int r = 0; r < Q::R; ++r) lds[lidx(p, o + r * Q::Ns)] = v[t * Q::R + r];
+        }
+    }
+
+    template <int S>
+    __device__ __forceinline__ static void read_lds(const float2* lds, float2* v, int p, int j) {
+        using Q = St<S>;
+#pragma unroll
+        for (int t = 0; t < Q::NB; ++t) {
+            const int b = j + t * T;
+            if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+#pragma unroll
+            for (int r = 0; r < Q::R; ++r) v[t * Q::R + r] = lds[lidx(p, b + r * Q::NBF)];
+        }
+    }
+
+    // Four-step twiddle and scale of output element e.
+    __device__ __forceinline__ static float2 finish(float2 x, int e, const Ctx& c, const PassArgs& a) {
+        if (a.tw4_mode != 0) {
+            // g < M/N and e < N, so g*e < M: no reduction needed.
+            const int64_t g = a.tw4_mode == 1 ? c.col : c.o1;
+            float2 w = a.tw4[g * e];
+            if (SIGN > 0) w.y = -w.y;
+            x = cmul(x, w);
+        }
+        return cscale(x, a.scale);
+    }
+
+    template <int S>
+    __device__ __forceinline__ static void store_last(float2* lds, float2* v, const Ctx& c,
+                                                      const PassArgs& a) {
+        using Q = St<S>;
+        if (STRIDED && a.tstore) {
+            // Results to LDS in natural element order, then each column leaves
+            // as one contiguous run of N elements.
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < Q::NB; ++t) {
+                const int b = c.j + t * T;
+                if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+#pragma unroll
+                for (int r = 0; r < Q::R; ++r) lds[lidx(c.p, b + r * Q::NBF)] = v[t * Q::R + r];
+            }
+            __syncthreads();
+            const int64_t c0 = c.col - c.p;
+            for (int idx = threadIdx.x; idx < N * P; idx += T * P) {
+                const int pl = idx / N, e = idx % N;
+                const int64_t col = c0 + pl;
+                if (col >= a.C) continue;
+                Ctx cc = c;
+                cc.col = col;
+                const float2 x = finish(lds[lidx(pl, e)], e, cc, a);
+                IO::store(a.dst, c.base_out - c.p * a.cs_out + pl * a.cs_out + (int64_t)e * a.es_out, x);
+            }
+            return;
+        }
+        if (!c.valid) return;
+        const int64_t es = STRIDED ? a.es_out : 1;
+#pragma unroll
+        for (int t = 0; t < Q::NB; ++t) {
+            const int b = c.j + t * T;
+            if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+#pragma unroll
+            for (int r = 0; r < Q::R; ++r) {
+                const int e = b + r * Q::NBF;
+                IO::store(a.dst, c.base_out + (int64_t)e * es, finish(v[t * Q::R + r], e, c, a));
+            }
+        }
+    }
+
+    // Stages S .. NS-1, data arriving in LDS.
+    template <int S>
+    __device__ __forceinline__ static void middle(float2* lds, float2* v, const Ctx& c, const PassArgs& a) {
+        if constexpr (S < NS) {
+            __syncthreads();
+            read_lds<S>(lds, v, c.p, c.j);
+            butterflies<S>(v, c.j, a.tw);
+            if constexpr (S + 1 < NS) {
+                __syncthreads();
+                write_lds<S>(lds, v, c.p, c.j);
+                middle<S + 1>(lds, v, c, a);
+            } else {
+                store_last<S>(lds, v, c, a);
+            }
+        }
+    }
+
+    __device__ __forceinline__ static void run(const PassArgs& a, float2* lds) {
+        const int tid = threadIdx.x;
+        Ctx c;
+        if constexpr (STRIDED) {
+            c.p = tid % P;
+            c.j = tid / P;
+            const int64_t ctiles = (a.C + P - 1) / P;
+            const int64_t t = blockIdx.x;
+            const int64_t rest = t / ctiles;
+            c.col = (t - rest * ctiles) * P + c.p;
+            c.o1 = rest % a.O1;
+            const int64_t o2 = rest / a.O1;
+            c.valid = c.col < a.C;
+            c.base_in = c.col + c.o1 * a.os1_in + o2 * a.os2_in;
+            c.base_out = c.col * a.cs_out + c.o1 * a.os1_out + o2 * a.os2_out;
+        } else {
+            c.j = tid % T;
+            c.p = tid / T;
+            c.col = (int64_t)blockIdx.x * P + c.p;
+            c.o1 = 0;
+            c.valid = c.col < a.C;
+            c.base_in = c.col * a.os1_in;
+            c.base_out = c.col * a.os1_out;
+        }
+        const int64_t es = STRIDED ? a.es_in : 1;
+
+        float2 v[maxv()];
+        {   // first stage straight from HBM
+            using Q = St<0>;
+#pragma unroll
+            for (int t = 0; t < Q::NB; ++t) {
+                const int b = c.j + t * T;
+                if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+#pragma unroll
+                for (int r = 0; r < Q::R; ++r)
+                    v[t * Q::R + r] = c.valid ? IO::load(a.src, c.base_in + (int64_t)(b + r * Q::NBF) * es)
+                                              : make_float2(0.f, 0.f);
+            }
+        }
+        butterflies<0>(v, c.j, a.tw);
+        if constexpr (NS == 1) {
+            store_last<0>(lds, v, c, a);
+        } else {
+            write_lds<0>(lds, v, c.p, c.j);
+            middle<1>(lds, v, c, a);
+        }
+    }
+};
+
+template <int N, int T, int P, bool STRIDED, class IO, int SIGN>
+__global__ __launch_bounds__(T * P) void pencil_pass_kernel(PassArgs a) {
+    extern __shared__ float2 lds_dyn[];
+    PencilPass<N, T, P, STRIDED, IO, SIGN>::run(a, lds_dyn);
+}
+
+}  // namespace wsfft

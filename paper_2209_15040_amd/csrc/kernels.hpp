@@ -1,0 +1,32 @@
+// Host-side registry of the compiled pencil-pass kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "fft_device.hpp"
+
+namespace wsfft {
+
+enum StorageKind { kC64 = 0, kF16 = 1, kBF16 = 2 };
+
+struct PassKernel {
+    int n;              // pencil length
+    bool strided;       // layout: columns unit-stride (true) or pencils contiguous
+    int threads;        // workgroup size
+    int per_block;      // pencils (contiguous) or columns (strided) per workgroup
+    int lds_bytes;      // dynamic LDS per workgroup
+    hipError_t (*launch)(const PassArgs&, dim3 grid, hipStream_t);
+    hipError_t (*prepare)();   // one-time function attributes
+};
+
+// NULL when no kernel of that length/layout exists.
+const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided);
+
+#define WSFFT_DECLARE_FIND(NAME) const PassKernel* NAME(int n, bool strided);
+WSFFT_DECLARE_FIND(find_pass_c64_neg)
+WSFFT_DECLARE_FIND(find_pass_c64_pos)
+WSFFT_DECLARE_FIND(find_pass_f16_neg)
+WSFFT_DECLARE_FIND(find_pass_f16_pos)
+WSFFT_DECLARE_FIND(find_pass_bf16_neg)
+WSFFT_DECLARE_FIND(find_pass_bf16_pos)
+#undef WSFFT_DECLARE_FIND
+
+}  // namespace wsfft

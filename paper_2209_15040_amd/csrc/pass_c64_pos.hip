@@ -1,0 +1,5 @@
+// Direct pencil-pass kernels: storage c64, transform sign 1.
+#define WSFFT_IO IoC64
+#define WSFFT_SIGN (1)
+#define WSFFT_FIND find_pass_c64_pos
+#include "pass_inst.inc"

@@ -1,0 +1,620 @@
+// C-ABI of the MI355X multidimensional FFT: plans, pass schedules, twiddle
+// tables and the execute entry points.  The interface is declared and
+// documented in include/wsfft.h.
+//
+// Schedule (paper, Section 1 and Section 2.2; redistribution as in Section
+// 4.3, done here by addressing): one pencil pass per axis of length > 1.  An
+// axis whose pencils are unit-stride runs in the contiguous layout, the others
+// in the strided layout (tiles of adjacent columns).  An axis too long for one
+// pass of its layout is split n = n1 * n2 (four-step, the decomposition the
+// paper suggests for very long 1D transforms in Section 8) into two passes:
+//   A: length-n1 DFTs over y1 of a[n2*y1 + y2], times W_n^(y2*k1),
+//      written to position k1 + n1*y2
+//   B: length-n2 DFTs over y2 of positions k1 + n1*y2, written in place,
+//      which leaves X[k1 + n1*k2] at position k1 + n1*k2.
+// Pass A cannot run in place, so split axes go first and read the input.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/wsfft.h"
+#include "kernels.hpp"
+#include "pass_config.hpp"
+
+using namespace wsfft;
+
+namespace {
+
+thread_local wsfft_status_t g_last_error = WSFFT_SUCCESS;
+
+std::mutex g_plans_mu;
+std::unordered_set<const wsfft_plan_s*> g_plans;
+
+struct Pass {
+    const PassKernel* kern_neg;   // kernel with sign -1
+    const PassKernel* kern_pos;   // kernel with sign +1
+    PassArgs args;                // src/dst/scale filled per call
+    int src_sel, dst_sel;         // 0 = caller input, 1 = caller output, 2 = work buffer
+    int src_sel_ip, dst_sel_ip;   // the same when the caller passes in == out
+    int axis;
+    int64_t n;
+    bool strided;
+    int four_step;                // 0 direct, 1 pass A, 2 pass B
+    int64_t tw_off, tw4_off;      // element offsets into the twiddle block (tw4: -1 none)
+    float pass_scale;             // 2^-s_p
+    int outer_dim;                // count whose stride spans whole arrays: 0 = C, 1 = O1, 2 = O2
+    dim3 grid;
+};
+
+bool is_smooth23(int64_t n) {
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+bool direct_ok(int64_t n, bool strided) {
+    return strided ? n <= kMaxStridedN : n <= kMaxContigN;
+}
+
+// Split n into n1 * n2 with both passes' lengths in the strided size range,
+// n1 as close to sqrt(n) as possible.  Returns false if impossible.
+bool split_axis(int64_t n, int64_t* n1, int64_t* n2) {
+    int64_t best = 0;
+    for (int64_t d = 2; d * d <= n; ++d) {
+        if (n % d) continue;
+        const int64_t e = n / d;
+        if (d <= kMaxStridedN && e <= kMaxStridedN) best = d;
+    }
+    if (!best) return false;
+    *n1 = best;            // the smaller factor, <= sqrt(n)
+    *n2 = n / best;
+    return true;
+}
+
+// Round x to a binary format with `mant` stored significand bits and
+// smallest normal exponent `emin`, nearest-even (subnormals included).
+double round_to_format(double x, int mant, int emin) {
+    if (x == 0.0) return 0.0;
+    int e2;
+    std::frexp(x, &e2);              // |x| in [2^(e2-1), 2^e2)
+    const int lead = std::max(e2 - 1, emin);
+    const double ulp = std::ldexp(1.0, lead - mant);
+    return std::nearbyint(x / ulp) * ulp;
+}
+
+// exp(-2*pi*i*m/n) in FP64, reduced to the first octant by exact integer
+// symmetry so that values on the axes and diagonals come out exact.
+void root_fp64(int64_t m, int64_t n, double* re, double* im) {
+    m %= n;
+    // angle = (pi/2) * (q + r/n) with integer quadrant q and 0 <= r < n
+    const int64_t u = 4 * m;
+    const int64_t q = u / n;
+    const int64_t r = u - q * n;
+    double c, s;
+    if (2 * r <= n) {
+        const double phi = (M_PI / 2) * (double)r / (double)n;
+        c = std::cos(phi);
+        s = std::sin(phi);
+    } else {
+        const double phi = (M_PI / 2) * (double)(n - r) / (double)n;
+        c = std::sin(phi);
+        s = std::cos(phi);
+    }
+    if (r == 0) { c = 1.0; s = 0.0; }
+    double cr, sr;   // rotate (c, s) by q quarter turns
+    switch (q & 3) {
+        case 0: cr = c; sr = s; break;
+        case 1: cr = -s; sr = c; break;
+        case 2: cr = -c; sr = -s; break;
+        default: cr = s; sr = -c; break;
+    }
+    *re = cr;
+    *im = -sr;   // forward kernel exp(-i*angle)
+}
+
+StorageKind kind_of(wsfft_dtype_t d) {
+    return d == WSFFT_C64 ? kC64 : (d == WSFFT_C16_FP16 ? kF16 : kBF16);
+}
+
+int elem_bytes(wsfft_dtype_t d) { return d == WSFFT_C64 ? 8 : 4; }
+
+}  // namespace
+
+struct wsfft_plan_s {
+    int64_t n[3];
+    wsfft_dtype_t dtype;
+    int sign;
+    unsigned flags;
+    int device;
+    int scale_log2;
+    std::vector<Pass> passes;
+    float2* tw_dev = nullptr;     // all twiddle tables, one block
+    void* work = nullptr;         // four-step work buffer (or null)
+    int64_t work_bytes = 0;
+    std::string desc;
+};
+
+namespace {
+
+bool plan_live(const wsfft_plan_s* p) {
+    if (!p) return false;
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    return g_plans.count(p) != 0;
+}
+
+wsfft_plan_t fail(wsfft_status_t st) {
+    g_last_error = st;
+    return nullptr;
+}
+
+// Geometry of one axis: `inner` = product of faster axes, `outer` = slower.
+struct AxisGeo {
+    int axis;
+    int64_t n, inner, outer;
+};
+
+void set_direct(Pass& P, const AxisGeo& g) {
+    PassArgs& a = P.args;
+    std::memset(&a, 0, sizeof a);
+    a.M = 1;
+    a.scale = 1.0f;
+    a.O1 = a.O2 = 1;
+    if (g.inner == 1) {            // contiguous pencils
+        P.strided = false;
+        P.outer_dim = 0;
+        a.C = g.outer;
+        a.es_in = a.es_out = 1;
+        a.os1_in = a.os1_out = g.n;
+        a.cs_out = 1;
+    } else {
+        P.strided = true;
+        P.outer_dim = 1;
+        a.C = g.inner;
+        a.O1 = g.outer;
+        a.es_in = a.es_out = g.inner;
+        a.os1_in = a.os1_out = g.inner * g.n;
+        a.cs_out = 1;
+    }
+}
+
+// Pass A and pass B of a split axis, see the file comment.
+void set_four_step(Pass& A, Pass& B, const AxisGeo& g, int64_t n1, int64_t n2) {
+    const int64_t I = g.inner, n = g.n;
+    for (Pass* P : {&A, &B}) {
+        std::memset(&P->args, 0, sizeof P->args);
+        P->args.scale = 1.0f;
+        P->args.M = n;
+        P->strided = true;
+    }
+    A.outer_dim = B.outer_dim = (I == 1) ? 1 : 2;
+    PassArgs& a = A.args;
+    if (I == 1) {
+        // columns y2 (unit stride), elements y1 at stride n2; output of
+        // column y2 is the contiguous run k1 + n1*y2.
+        a.C = n2; a.O1 = g.outer; a.O2 = 1;
+        a.es_in = n2; a.os1_in = n;
+        a.es_out = 1; a.cs_out = n1; a.os1_out = n;
+        a.tw4_mode = 1;
+        a.tstore = 1;
+    } else {
+        // columns are the faster axes (unit stride); y2 is outer index 1.
+        a.C = I; a.O1 = n2; a.O2 = g.outer;
+        a.es_in = n2 * I; a.os1_in = I; a.os2_in = I * n;
+        a.es_out = I; a.cs_out = 1; a.os1_out = n1 * I; a.os2_out = I * n;
+        a.tw4_mode = 2;
+    }
+    PassArgs& b = B.args;
+    if (I == 1) {
+        b.C = n1; b.O1 = g.outer; b.O2 = 1;
+        b.es_in = b.es_out = n1; b.os1_in = b.os1_out = n; b.cs_out = 1;
+    } else {
+        b.C = I; b.O1 = n1; b.O2 = g.outer;
+        b.es_in = b.es_out = n1 * I;
+        b.os1_in = b.os1_out = I;
+        b.os2_in = b.os2_out = I * n;
+        b.cs_out = 1;
+    }
+}
+
+int64_t blocks_for(const Pass& P, const PassKernel* k) {
+    const PassArgs& a = P.args;
+    if (P.strided) return ((a.C + k->per_block - 1) / k->per_block) * a.O1 * a.O2;
+    return (a.C + k->per_block - 1) / k->per_block;
+}
+
+const char* kind_name(wsfft_dtype_t d) {
+    return d == WSFFT_C64 ? "c64" : (d == WSFFT_C16_FP16 ? "c16-fp16" : "c16-bf16");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wsfft_status_string(wsfft_status_t st) {
+    switch (st) {
+        case WSFFT_SUCCESS: return "success";
+        case WSFFT_ERROR_INVALID_VALUE: return "invalid value";
+        case WSFFT_ERROR_UNSUPPORTED_SIZE: return "unsupported size";
+        case WSFFT_ERROR_NULL_POINTER: return "null pointer";
+        case WSFFT_ERROR_MISALIGNED: return "misaligned pointer";
+        case WSFFT_ERROR_OUT_OF_MEMORY: return "out of device memory";
+        case WSFFT_ERROR_NO_DEVICE: return "no HIP device";
+        case WSFFT_ERROR_HIP: return "HIP runtime error";
+        case WSFFT_ERROR_INVALID_PLAN: return "invalid plan";
+        case WSFFT_ERROR_WRONG_DEVICE: return "current device is not the plan's device";
+    }
+    return "unknown status";
+}
+
+wsfft_status_t wsfft_get_last_error(void) { return g_last_error; }
+
+wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtype_t dtype, int sign,
+                                  unsigned flags) {
+    // ---- argument checks, no device calls -------------------------------
+    if (nx < 1 || ny < 1 || nz < 1) return fail(WSFFT_ERROR_INVALID_VALUE);
+    if (sign != 1 && sign != -1) return fail(WSFFT_ERROR_INVALID_VALUE);
+    if (dtype != WSFFT_C64 && dtype != WSFFT_C16_FP16 && dtype != WSFFT_C16_BF16)
+        return fail(WSFFT_ERROR_INVALID_VALUE);
+    if (flags & ~WSFFT_FLAG_FP32_TWIDDLES) return fail(WSFFT_ERROR_INVALID_VALUE);
+    const int64_t dims[3] = {nx, ny, nz};
+    for (int64_t d : dims)
+        if (d > WSFFT_MAX_AXIS || !is_smooth23(d)) return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+    if (nx * ny > (int64_t(1) << 40) || nx * ny * nz > (int64_t(1) << 40))
+        return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+
+    wsfft_plan_s* plan = new (std::nothrow) wsfft_plan_s();
+    if (!plan) return fail(WSFFT_ERROR_OUT_OF_MEMORY);
+    plan->n[0] = nx; plan->n[1] = ny; plan->n[2] = nz;
+    plan->dtype = dtype;
+    plan->sign = sign;
+    plan->flags = flags;
+
+    // ---- schedule --------------------------------------------------------
+    const bool half = dtype != WSFFT_C64;
+    std::vector<AxisGeo> direct, split;
+    const AxisGeo geos[3] = {{0, nx, 1, ny * nz}, {1, ny, nx, nz}, {2, nz, nx * ny, 1}};
+    for (const AxisGeo& g : geos) {
+        if (g.n == 1) continue;
+        if (direct_ok(g.n, g.inner != 1)) direct.push_back(g);
+        else split.push_back(g);
+    }
+    std::vector<AxisGeo> order = split;   // split axes first: pass A reads the input
+    order.insert(order.end(), direct.begin(), direct.end());
+
+    // twiddle tables: (length, offset) for every distinct length
+    std::vector<std::pair<int64_t, int64_t>> tables;
+    int64_t tw_total = 0;
+    auto table_for = [&](int64_t len) -> int64_t {
+        for (auto& t : tables)
+            if (t.first == len) return t.second;
+        tables.push_back({len, tw_total});
+        tw_total += len;
+        return tables.back().second;
+    };
+
+    const StorageKind kind = kind_of(dtype);
+    int S = 0;
+    for (const AxisGeo& g : order) {
+        const bool is_split = !direct_ok(g.n, g.inner != 1);
+        const int sp = half ? (int)std::ceil(std::log2((double)g.n) / 2.0) : 0;
+        S += sp;
+        if (!is_split) {
+            Pass P{};
+            set_direct(P, g);
+            P.axis = g.axis; P.n = g.n; P.four_step = 0;
+            P.tw_off = table_for(g.n); P.tw4_off = -1;
+            P.pass_scale = std::ldexp(1.0f, -sp);
+            plan->passes.push_back(P);
+        } else {
+            int64_t n1, n2;
+            if (!split_axis(g.n, &n1, &n2)) { delete plan; return fail(WSFFT_ERROR_UNSUPPORTED_SIZE); }
+            Pass A{}, B{};
+            set_four_step(A, B, g, n1, n2);
+            A.axis = B.axis = g.axis;
+            A.n = n1; B.n = n2;
+            A.four_step = 1; B.four_step = 2;
+            A.tw_off = table_for(n1); B.tw_off = table_for(n2);
+            A.tw4_off = table_for(g.n); B.tw4_off = -1;
+            // the axis scale 2^-sp is split between the two passes
+            const int sa = sp / 2, sb = sp - sa;
+            A.pass_scale = std::ldexp(1.0f, -sa);
+            B.pass_scale = std::ldexp(1.0f, -sb);
+            plan->passes.push_back(A);
+            plan->passes.push_back(B);
+        }
+    }
+    plan->scale_log2 = S;
+
+    // kernels
+    for (Pass& P : plan->passes) {
+        P.kern_neg = find_pass_kernel(kind, -1, (int)P.n, P.strided);
+        P.kern_pos = find_pass_kernel(kind, +1, (int)P.n, P.strided);
+        if (!P.kern_neg || !P.kern_pos) { delete plan; return fail(WSFFT_ERROR_UNSUPPORTED_SIZE); }
+        // one grid dimension holds at most 2^32 - 1 work-items
+        const int64_t blocks = blocks_for(P, P.kern_neg);
+        if (blocks < 1 || blocks * P.kern_neg->threads > 0xffffffffLL) {
+            delete plan;
+            return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+        }
+        P.grid = dim3((unsigned)blocks);
+    }
+
+    // buffers: split passes read the caller's input (first) or, for a
+    // second split axis, the work buffer
+    int nsplit = 0;
+    for (size_t i = 0; i < plan->passes.size(); ++i) {
+        Pass& P = plan->passes[i];
+        if (i == 0) { P.src_sel = 0; P.dst_sel = 1; }
+        else { P.src_sel = 1; P.dst_sel = 1; }
+        if (P.four_step == 1) {
+            if (nsplit > 0) { P.src_sel = 1; P.dst_sel = 2; }
+            ++nsplit;
+        } else if (P.four_step == 2 && nsplit > 1) {
+            P.src_sel = 2; P.dst_sel = 1;
+        }
+    }
+    // In-place calls: the first split axis goes through the work buffer too.
+    for (size_t i = 0; i < plan->passes.size(); ++i) {
+        Pass& P = plan->passes[i];
+        P.src_sel_ip = P.src_sel;
+        P.dst_sel_ip = P.dst_sel;
+        if (nsplit > 1 && i == 0 && P.four_step == 1) P.dst_sel_ip = 2;
+        if (nsplit > 1 && i == 1 && P.four_step == 2) P.src_sel_ip = 2;
+    }
+    const int64_t N = nx * ny * nz;
+    if (nsplit > 1) plan->work_bytes = N * elem_bytes(dtype);
+
+    // description
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%lldx%lldx%lld %s sign=%d S=%d:", (long long)nx, (long long)ny,
+                  (long long)nz, kind_name(dtype), sign, S);
+    plan->desc = buf;
+    for (const Pass& P : plan->passes) {
+        std::snprintf(buf, sizeof buf, " %c%s[%s n=%lld wg=%d per=%d lds=%d grid=%u]", "xyz"[P.axis],
+                      P.four_step == 1 ? "A" : (P.four_step == 2 ? "B" : ""),
+                      P.strided ? "strided" : "contig", (long long)P.n, P.kern_neg->threads,
+                      P.kern_neg->per_block, P.kern_neg->lds_bytes, P.grid.x);
+        plan->desc += buf;
+    }
+
+    // ---- device ------------------------------------------------------------
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { delete plan; return fail(WSFFT_ERROR_NO_DEVICE); }
+    if (hipGetDevice(&plan->device) != hipSuccess) { delete plan; return fail(WSFFT_ERROR_HIP); }
+
+    // twiddles in FP64, rounded once to the table precision
+    const bool tw32 = !half || (flags & WSFFT_FLAG_FP32_TWIDDLES);
+    const int mant = tw32 ? 23 : (dtype == WSFFT_C16_FP16 ? 10 : 7);
+    const int emin = tw32 ? -126 : (dtype == WSFFT_C16_FP16 ? -14 : -126);
+    std::vector<float2> host((size_t)std::max<int64_t>(tw_total, 1));
+    for (auto& t : tables) {
+        for (int64_t m = 0; m < t.first; ++m) {
+            double re, im;
+            root_fp64(m, t.first, &re, &im);
+            host[(size_t)(t.second + m)] = make_float2((float)round_to_format(re, mant, emin),
+                                                       (float)round_to_format(im, mant, emin));
+        }
+    }
+    if (hipMalloc(&plan->tw_dev, host.size() * sizeof(float2)) != hipSuccess) {
+        delete plan;
+        return fail(WSFFT_ERROR_OUT_OF_MEMORY);
+    }
+    if (hipMemcpy(plan->tw_dev, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(plan->tw_dev);
+        delete plan;
+        return fail(WSFFT_ERROR_HIP);
+    }
+    if (plan->work_bytes > 0 && hipMalloc(&plan->work, (size_t)plan->work_bytes) != hipSuccess) {
+        (void)hipFree(plan->tw_dev);
+        delete plan;
+        return fail(WSFFT_ERROR_OUT_OF_MEMORY);
+    }
+    for (Pass& P : plan->passes) {
+        P.args.tw = plan->tw_dev + P.tw_off;
+        P.args.tw4 = P.tw4_off >= 0 ? plan->tw_dev + P.tw4_off : nullptr;
+        if (P.kern_neg->prepare() != hipSuccess || P.kern_pos->prepare() != hipSuccess) {
+            (void)hipFree(plan->tw_dev);
+            if (plan->work) (void)hipFree(plan->work);
+            delete plan;
+            return fail(WSFFT_ERROR_HIP);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> g(g_plans_mu);
+        g_plans.insert(plan);
+    }
+    g_last_error = WSFFT_SUCCESS;
+    return plan;
+}
+
+wsfft_plan_t wsfft_plan_create(int64_t nx, int64_t ny, int64_t nz, wsfft_dtype_t dtype, int sign) {
+    return wsfft_plan_create_ex(nx, ny, nz, dtype, sign, 0u);
+}
+
+int wsfft_plan_scale_log2(wsfft_plan_t plan) { return plan_live(plan) ? plan->scale_log2 : -1; }
+
+int wsfft_plan_num_passes(wsfft_plan_t plan) { return plan_live(plan) ? (int)plan->passes.size() : -1; }
+
+int64_t wsfft_plan_work_bytes(wsfft_plan_t plan) { return plan_live(plan) ? plan->work_bytes : -1; }
+
+wsfft_status_t wsfft_plan_describe(wsfft_plan_t plan, char* buf, size_t len) {
+    if (!plan_live(plan)) return WSFFT_ERROR_INVALID_PLAN;
+    if (!buf) return WSFFT_ERROR_NULL_POINTER;
+    if (len == 0) return WSFFT_ERROR_INVALID_VALUE;
+    std::snprintf(buf, len, "%s", plan->desc.c_str());
+    return WSFFT_SUCCESS;
+}
+
+void wsfft_plan_destroy(wsfft_plan_t plan) {
+    if (!plan) return;
+    {
+        std::lock_guard<std::mutex> g(g_plans_mu);
+        if (!g_plans.erase(plan)) return;   // unknown or already destroyed
+    }
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(plan->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(plan->tw_dev);
+    if (plan->work) (void)hipFree(plan->work);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    delete plan;
+}
+
+}  // extern "C"
+
+// ---- execution -----------------------------------------------------------
+namespace {
+
+// mode: 0 = plan sign, 1 = opposite sign (adjoint), 2 = opposite sign / N
+wsfft_status_t check_exec(const wsfft_plan_s* plan, const void* in, const void* out) {
+    if (!plan_live(plan)) return WSFFT_ERROR_INVALID_PLAN;
+    if (!in || !out) return WSFFT_ERROR_NULL_POINTER;
+    const uintptr_t al = (uintptr_t)elem_bytes(plan->dtype);
+    if (((uintptr_t)in % al) || ((uintptr_t)out % al)) return WSFFT_ERROR_MISALIGNED;
+    // a split axis reading the input cannot run in place without the work buffer
+    if (in == out && plan->work_bytes == 0)
+        for (const Pass& P : plan->passes)
+            if (P.four_step == 1 && P.src_sel == 0) return WSFFT_ERROR_INVALID_VALUE;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
+    if (cur != plan->device) return WSFFT_ERROR_WRONG_DEVICE;
+    return WSFFT_SUCCESS;
+}
+
+// Enqueue pass index `pi` of a plan; returns false on a launch error.
+bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out, int mode,
+                 hipStream_t stream, int64_t batch = 1) {
+    const Pass& P = plan->passes[pi];
+    PassArgs a = P.args;
+    dim3 grid = P.grid;
+    if (batch > 1) {   // `batch` arrays back to back: one more factor on the outermost count
+        int64_t blocks;
+        const int64_t per = P.kern_neg->per_block;
+        if (P.outer_dim == 0) a.C *= batch;
+        else if (P.outer_dim == 1) a.O1 *= batch;
+        else a.O2 *= batch;
+        if (P.strided) blocks = ((a.C + per - 1) / per) * a.O1 * a.O2;
+        else blocks = (a.C + per - 1) / per;
+        if (blocks * P.kern_neg->threads > 0xffffffffLL) return false;
+        grid = dim3((unsigned)blocks);
+    }
+    auto sel = [&](int s) -> void* {
+        return s == 0 ? const_cast<void*>(in) : (s == 1 ? out : plan->work);
+    };
+    const bool ip = in == out;
+    a.src = sel(ip ? P.src_sel_ip : P.src_sel);
+    a.dst = sel(ip ? P.dst_sel_ip : P.dst_sel);
+    a.scale = P.pass_scale;
+    if (mode == 2 && pi + 1 == plan->passes.size()) {
+        const double N = (double)plan->n[0] * (double)plan->n[1] * (double)plan->n[2];
+        a.scale = (float)((double)P.pass_scale / N);
+    }
+    const int sign = mode == 0 ? plan->sign : -plan->sign;
+    const PassKernel* k = sign < 0 ? P.kern_neg : P.kern_pos;
+    return k->launch(a, grid, stream) == hipSuccess;
+}
+
+wsfft_status_t exec_plan(const wsfft_plan_s* plan, const void* in, void* out, int mode, hipStream_t stream) {
+    if (plan->passes.empty()) {   // every axis has length 1: the DFT is the identity
+        if (in != out &&
+            hipMemcpyAsync(out, in, (size_t)elem_bytes(plan->dtype), hipMemcpyDeviceToDevice, stream) != hipSuccess)
+            return WSFFT_ERROR_HIP;
+        return WSFFT_SUCCESS;
+    }
+    for (size_t i = 0; i < plan->passes.size(); ++i)
+        if (!launch_pass(plan, i, in, out, mode, stream)) return WSFFT_ERROR_HIP;
+    return WSFFT_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+wsfft_status_t wsfft_execute(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream) {
+    const wsfft_status_t st = check_exec(plan, in, out);
+    return st != WSFFT_SUCCESS ? st : exec_plan(plan, in, out, 0, stream);
+}
+
+wsfft_status_t wsfft_execute_adjoint(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream) {
+    const wsfft_status_t st = check_exec(plan, in, out);
+    return st != WSFFT_SUCCESS ? st : exec_plan(plan, in, out, 1, stream);
+}
+
+wsfft_status_t wsfft_execute_inverse(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream) {
+    const wsfft_status_t st = check_exec(plan, in, out);
+    return st != WSFFT_SUCCESS ? st : exec_plan(plan, in, out, 2, stream);
+}
+
+wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const void* in, void* out,
+                                  hipStream_t stream) {
+    const wsfft_status_t st = check_exec(plan, in, out);
+    if (st != WSFFT_SUCCESS) return st;
+    if (mode < 0 || mode > 2 || index < 0 || (size_t)index >= plan->passes.size()) return WSFFT_ERROR_INVALID_VALUE;
+    return launch_pass(plan, (size_t)index, in, out, mode, stream) ? WSFFT_SUCCESS : WSFFT_ERROR_HIP;
+}
+
+wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const void* const* in,
+                                     void* const* out, int adjoint, hipStream_t stream) {
+    if (count < 0) return WSFFT_ERROR_INVALID_VALUE;
+    if (count == 0) return WSFFT_SUCCESS;
+    if (!plans || !in || !out) return WSFFT_ERROR_NULL_POINTER;
+    size_t maxp = 0;
+    for (int i = 0; i < count; ++i) {
+        const wsfft_status_t st = check_exec(plans[i], in[i], out[i]);
+        if (st != WSFFT_SUCCESS) return st;
+        if (plans[i]->dtype != plans[0]->dtype) return WSFFT_ERROR_INVALID_VALUE;
+        if (plans[i]->work_bytes > 0) return WSFFT_ERROR_INVALID_VALUE;
+        maxp = std::max(maxp, plans[i]->passes.size());
+    }
+    const int mode = adjoint ? 1 : 0;
+    // One plan over arrays spaced exactly one array apart, in and out alike:
+    // the batch is one larger array whose slowest axis is not transformed.
+    bool uniform = count > 1 && !plans[0]->passes.empty();
+    const int64_t N = plans[0]->n[0] * plans[0]->n[1] * plans[0]->n[2];
+    const intptr_t span = (intptr_t)(N * elem_bytes(plans[0]->dtype));
+    for (int i = 1; uniform && i < count; ++i)
+        uniform = plans[i] == plans[0] &&
+                  (const char*)in[i] - (const char*)in[0] == (intptr_t)i * span &&
+                  (const char*)out[i] - (const char*)out[0] == (intptr_t)i * span;
+    if (uniform && (in[0] == out[0] || (const char*)out[0] >= (const char*)in[0] + span * count ||
+                    (const char*)in[0] >= (const char*)out[0] + span * count)) {
+        for (size_t pi = 0; pi < plans[0]->passes.size(); ++pi)
+            if (!launch_pass(plans[0], pi, in[0], out[0], mode, stream, count)) return WSFFT_ERROR_HIP;
+        return WSFFT_SUCCESS;
+    }
+    // identity plans first, then pass-major order over the batch
+    for (int i = 0; i < count; ++i)
+        if (plans[i]->passes.empty()) {
+            const wsfft_status_t st = exec_plan(plans[i], in[i], out[i], mode, stream);
+            if (st != WSFFT_SUCCESS) return st;
+        }
+    for (size_t pi = 0; pi < maxp; ++pi)
+        for (int i = 0; i < count; ++i)
+            if (pi < plans[i]->passes.size() && !launch_pass(plans[i], pi, in[i], out[i], mode, stream))
+                return WSFFT_ERROR_HIP;
+    return WSFFT_SUCCESS;
+}
+
+}  // extern "C"
+
+namespace wsfft {
+
+const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided) {
+    switch (kind) {
+        case kC64: return sign < 0 ? find_pass_c64_neg(n, strided) : find_pass_c64_pos(n, strided);
+        case kF16: return sign < 0 ? find_pass_f16_neg(n, strided) : find_pass_f16_pos(n, strided);
+        case kBF16: return sign < 0 ? find_pass_bf16_neg(n, strided) : find_pass_bf16_pos(n, strided);
+    }
+    return nullptr;
+}
+
+}  // namespace wsfft
