@@ -176,6 +176,8 @@ constexpr int stage_ns(const Radices& R, int s) {
 }
 
 // --------------------------------------------------------- storage types ---
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 struct IoC64 {   // complex64: FP32 re, FP32 im
     static constexpr int bytes = 8;
     static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
@@ -183,6 +185,17 @@ struct IoC64 {   // complex64: FP32 re, FP32 im
     }
     static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
         reinterpret_cast<float2*>(p)[i] = v;
+    }
+    // streaming variants: data touched once per pass, no reuse in cache
+    static __device__ __forceinline__ float2 load_nt(const void* p, int64_t i) {
+        const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p) + i);
+        return make_float2(v.x, v.y);
+    }
+    static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
+        f32x2 w;
+        w.x = v.x;
+        w.y = v.y;
+        __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(p) + i);
     }
 };
 
@@ -194,6 +207,14 @@ struct IoF16 {   // FP16 re, FP16 im
     }
     static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
         reinterpret_cast<__half2*>(p)[i] = __float22half2_rn(v);
+    }
+    static __device__ __forceinline__ float2 load_nt(const void* p, int64_t i) {
+        const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p) + i);
+        return __half22float2(__builtin_bit_cast(__half2, w));
+    }
+    static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, __float22half2_rn(v)),
+                                    reinterpret_cast<uint32_t*>(p) + i);
     }
 };
 
@@ -213,7 +234,36 @@ struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
     static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
         reinterpret_cast<uint32_t*>(p)[i] = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
     }
+    static __device__ __forceinline__ float2 load_nt(const void* p, int64_t i) {
+        const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p) + i);
+        return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+    }
+    static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
+        __builtin_nontemporal_store(f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16),
+                                    reinterpret_cast<uint32_t*>(p) + i);
+    }
 };
+
+// Kernel feature flags (template parameter FLAGS).
+enum : int {
+    kFlagNontemporal = 1,   // streaming (non-temporal) global loads and stores
+    kFlagXcdOrder = 2,      // consecutive tiles on one XCD (the hardware deals
+                            // workgroups round-robin over the 8 XCDs)
+    kFlagPersistent = 4,    // one resident grid walks all tiles; the next tile's
+                            // inputs load while the current one is transformed,
+                            // and the twiddle table sits in LDS so no global
+                            // load waits behind that prefetch
+    kFlagFourStep = 8,      // first pass of a split axis: inter-pass twiddles
+                            // and the transposed store (PassArgs tw4_mode,
+                            // tstore) are compiled in only with this flag
+};
+
+// Workgroup id -> tile id such that each XCD gets one contiguous range of
+// tiles: XCD x = b mod 8 runs tiles [x*q + min(x, r), ...) in order.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+    const int64_t q = G / 8, r = G % 8, x = b % 8, i = b / 8;
+    return x * q + (x < r ? x : r) + i;
+}
 
 // -------------------------------------------------------------- pass args ---
 // A pass transforms pencils of length N.  Two layouts:
@@ -238,16 +288,34 @@ struct PassArgs {
 };
 
 // ------------------------------------------------------------ the kernel ---
-template <int N, int T, int P, bool STRIDED, class IO, int SIGN>
+// N: pencil length.  T: threads per pencil.  P: pencils (contiguous layout)
+// or columns (strided layout) per workgroup.  K: the strided layout's LDS
+// exchanges run in K rounds over N/K rows each, so a wide tile needs only
+// 1/K of its size in LDS and more workgroups stay resident per CU.
+template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1>
 struct PencilPass {
+    static_assert(STRIDED || K == 1, "split exchanges are for the strided layout");
+    static_assert(N % K == 0, "K must divide N");
+    static constexpr bool NT = (FLAGS & kFlagNontemporal) != 0;
+    static constexpr bool PERSIST = (FLAGS & kFlagPersistent) != 0;
+    static constexpr bool FOURSTEP = (FLAGS & kFlagFourStep) != 0;
+    __device__ __forceinline__ static float2 gload(const void* p, int64_t i) {
+        if constexpr (NT) return IO::load_nt(p, i);
+        else return IO::load(p, i);
+    }
+    __device__ __forceinline__ static void gstore(void* p, int64_t i, float2 v) {
+        if constexpr (NT) IO::store_nt(p, i, v);
+        else IO::store(p, i, v);
+    }
     static constexpr Radices RD = make_radices(N);
     static constexpr int NS = RD.n;
+    static constexpr int ROWS = N / K;   // LDS rows per exchange round
     // LDS layout: strided tiles store [element][column], contiguous tiles
     // [pencil][element]; one float2 of padding per row breaks power-of-two
     // bank strides.
     static constexpr int LDS_ROW = STRIDED ? (P + 1) : (N + 1);
-    static constexpr int LDS_ELEMS = STRIDED ? N * (P + 1) : P * (N + 1);
-    static constexpr int lds_bytes() { return LDS_ELEMS * 8; }
+    static constexpr int LDS_ELEMS = STRIDED ? ROWS * (P + 1) : P * (N + 1);
+    static constexpr int lds_bytes() { return (LDS_ELEMS + (PERSIST ? N : 0)) * 8; }
     static constexpr int threads() { return T * P; }
 
     template <int S> struct St {
@@ -256,6 +324,7 @@ struct PencilPass {
         static constexpr int NBF = N / R;               // butterflies
         static constexpr int NB = (NBF + T - 1) / T;    // per thread
         static constexpr int TWS = N / (Ns * R);        // twiddle table stride
+        static constexpr bool FULL = NB * T == NBF;     // every thread busy
     };
 
     static constexpr int maxv() {
@@ -281,12 +350,12 @@ struct PencilPass {
     };
 
     template <int S>
-    __device__ __forceinline__ static void butterflies(float2* v, int j, const float2* __restrict__ tw) {
+    __device__ __forceinline__ static void butterflies(float2* v, int j, const float2* tw) {
         using Q = St<S>;
 #pragma unroll
         for (int t = 0; t < Q::NB; ++t) {
             const int b = j + t * T;
-            if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+            if (!Q::FULL && b >= Q::NBF) continue;
             float2* u = v + t * Q::R;
             if (S > 0) {
                 const int k = b % Q::Ns;
@@ -301,111 +370,164 @@ struct PencilPass {
         }
     }
 
+    // Stage S outputs (vo) -> stage S+1 inputs (vi) through LDS, in K rounds
+    // of ROWS rows.  lead: the LDS may still be read by the previous exchange.
     template <int S>
-    __device__ __forceinline__ static void write_lds(float2* lds, const float2* v, int p, int j) {
+    __device__ __forceinline__ static void exchange(float2* lds, const float2* vo, float2* vi, int p, int j,
+                                                    bool lead) {
         using Q = St<S>;
+        using Q2 = St<S + 1>;
 #pragma unroll
-        for (int t = 0; t < Q::NB; ++t) {
-            const int b = j + t * T;
-            if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
-            const int k = b % Q::Ns;
-            const int o = (b / Q::Ns) * Q::Ns * Q::R + k;
-#pragma unroll
-            for (int r = 0; r < Q::R; ++r) lds[lidx(p, o + r * Q::Ns)] = v[t * Q::R + r];
-        }
-    }
-
-    template <int S>
-    __device__ __forceinline__ static void read_lds(const float2* lds, float2* v, int p, int j) {
-        using Q = St<S>;
-#pragma unroll
-        for (int t = 0; t < Q::NB; ++t) {
-            const int b = j + t * T;
-            if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
-#pragma unroll
-            for (int r = 0; r < Q::R; ++r) v[t * Q::R + r] = lds[lidx(p, b + r * Q::NBF)];
-        }
-    }
-
-    // Four-step twiddle and scale of output element e.
-    __device__ __forceinline__ static float2 finish(float2 x, int e, const Ctx& c, const PassArgs& a) {
-        if (a.tw4_mode != 0) {
-            // g < M/N and e < N, so g*e < M: no reduction needed.
-            const int64_t g = a.tw4_mode == 1 ? c.col : c.o1;
-            float2 w = a.tw4[g * e];
-            if (SIGN > 0) w.y = -w.y;
-            x = cmul(x, w);
-        }
-        return cscale(x, a.scale);
-    }
-
-    template <int S>
-    __device__ __forceinline__ static void store_last(float2* lds, float2* v, const Ctx& c,
-                                                      const PassArgs& a) {
-        using Q = St<S>;
-        if (STRIDED && a.tstore) {
-            // Results to LDS in natural element order, then each column leaves
-            // as one contiguous run of N elements.
-            __syncthreads();
+        for (int h = 0; h < K; ++h) {
+            if (lead || h > 0) __syncthreads();
 #pragma unroll
             for (int t = 0; t < Q::NB; ++t) {
-                const int b = c.j + t * T;
-                if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+                const int b = j + t * T;
+                if (!Q::FULL && b >= Q::NBF) continue;
+                const int o = (b / Q::Ns) * Q::Ns * Q::R + b % Q::Ns;
 #pragma unroll
-                for (int r = 0; r < Q::R; ++r) lds[lidx(c.p, b + r * Q::NBF)] = v[t * Q::R + r];
+                for (int r = 0; r < Q::R; ++r) {
+                    const int e = o + r * Q::Ns;
+                    if (K == 1 || e / ROWS == h) lds[lidx(p, e - h * ROWS)] = vo[t * Q::R + r];
+                }
             }
             __syncthreads();
+#pragma unroll
+            for (int t = 0; t < Q2::NB; ++t) {
+                const int b = j + t * T;
+                if (!Q2::FULL && b >= Q2::NBF) continue;
+#pragma unroll
+                for (int r = 0; r < Q2::R; ++r) {
+                    const int e = b + r * Q2::NBF;
+                    if (K == 1 || e / ROWS == h) vi[t * Q2::R + r] = lds[lidx(p, e - h * ROWS)];
+                }
+            }
+        }
+    }
+
+    // Four-step twiddle of output element e (tw4_mode != 0).  g < M/N and
+    // e < N, so g*e < M: no reduction needed.
+    __device__ __forceinline__ static float2 tw4_of(int e, int64_t col, int64_t o1, const PassArgs& a) {
+        const int64_t g = a.tw4_mode == 1 ? col : o1;
+        float2 w = a.tw4[g * e];
+        if (SIGN > 0) w.y = -w.y;
+        return w;
+    }
+
+    template <int S>
+    __device__ __forceinline__ static void store_last(float2* lds, const float2* v, const Ctx& c,
+                                                      const PassArgs& a) {
+        using Q = St<S>;
+        if (FOURSTEP && STRIDED && a.tstore) {
+            // Results go to LDS in natural element order, ROWS rows per round,
+            // and each column leaves as contiguous runs of ROWS elements.
             const int64_t c0 = c.col - c.p;
-            for (int idx = threadIdx.x; idx < N * P; idx += T * P) {
-                const int pl = idx / N, e = idx % N;
-                const int64_t col = c0 + pl;
-                if (col >= a.C) continue;
-                Ctx cc = c;
-                cc.col = col;
-                const float2 x = finish(lds[lidx(pl, e)], e, cc, a);
-                IO::store(a.dst, c.base_out - c.p * a.cs_out + pl * a.cs_out + (int64_t)e * a.es_out, x);
+            const int64_t b0 = c.base_out - c.p * a.cs_out;
+#pragma unroll
+            for (int h = 0; h < K; ++h) {
+                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < Q::NB; ++t) {
+                    const int b = c.j + t * T;
+                    if (!Q::FULL && b >= Q::NBF) continue;
+#pragma unroll
+                    for (int r = 0; r < Q::R; ++r) {
+                        const int e = b + r * Q::NBF;
+                        if (K == 1 || e / ROWS == h) lds[lidx(c.p, e - h * ROWS)] = v[t * Q::R + r];
+                    }
+                }
+                // each thread stores PER elements of this round; their
+                // twiddles are all requested before the first use
+                constexpr int PER = (ROWS * P + T * P - 1) / (T * P);
+                float2 w4[PER];
+                if (FOURSTEP && a.tw4_mode != 0) {
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) {
+                        const int idx = threadIdx.x + i * T * P;
+                        const int pl = idx / ROWS, el = idx % ROWS;
+                        w4[i] = (idx < ROWS * P && c0 + pl < a.C) ? tw4_of(el + h * ROWS, c0 + pl, c.o1, a)
+                                                                  : make_float2(1.f, 0.f);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < PER; ++i) {
+                    const int idx = threadIdx.x + i * T * P;
+                    if (idx >= ROWS * P) continue;
+                    const int pl = idx / ROWS, el = idx % ROWS, e = el + h * ROWS;
+                    const int64_t col = c0 + pl;
+                    if (col >= a.C) continue;
+                    float2 x = lds[lidx(pl, el)];
+                    if (FOURSTEP && a.tw4_mode != 0) x = cmul(x, w4[i]);
+                    gstore(a.dst, b0 + pl * a.cs_out + (int64_t)e * a.es_out, cscale(x, a.scale));
+                }
             }
             return;
         }
         if (!c.valid) return;
         const int64_t es = STRIDED ? a.es_out : 1;
+        if (FOURSTEP && a.tw4_mode != 0) {
+            // all twiddle requests first, then the stores
+            float2 w4[Q::NB * Q::R];
+#pragma unroll
+            for (int t = 0; t < Q::NB; ++t) {
+                const int b = c.j + t * T;
+#pragma unroll
+                for (int r = 0; r < Q::R; ++r)
+                    w4[t * Q::R + r] = (Q::FULL || b < Q::NBF) ? tw4_of(b + r * Q::NBF, c.col, c.o1, a)
+                                                               : make_float2(1.f, 0.f);
+            }
+#pragma unroll
+            for (int t = 0; t < Q::NB; ++t) {
+                const int b = c.j + t * T;
+                if (!Q::FULL && b >= Q::NBF) continue;
+#pragma unroll
+                for (int r = 0; r < Q::R; ++r) {
+                    const int e = b + r * Q::NBF;
+                    gstore(a.dst, c.base_out + (int64_t)e * es,
+                           cscale(cmul(v[t * Q::R + r], w4[t * Q::R + r]), a.scale));
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int t = 0; t < Q::NB; ++t) {
             const int b = c.j + t * T;
-            if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+            if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
             for (int r = 0; r < Q::R; ++r) {
                 const int e = b + r * Q::NBF;
-                IO::store(a.dst, c.base_out + (int64_t)e * es, finish(v[t * Q::R + r], e, c, a));
+                gstore(a.dst, c.base_out + (int64_t)e * es, cscale(v[t * Q::R + r], a.scale));
             }
         }
     }
 
-    // Stages S .. NS-1, data arriving in LDS.
+    // Stages S .. NS-1; v holds the inputs of stage S.
     template <int S>
-    __device__ __forceinline__ static void middle(float2* lds, float2* v, const Ctx& c, const PassArgs& a) {
-        if constexpr (S < NS) {
-            __syncthreads();
-            read_lds<S>(lds, v, c.p, c.j);
-            butterflies<S>(v, c.j, a.tw);
-            if constexpr (S + 1 < NS) {
-                __syncthreads();
-                write_lds<S>(lds, v, c.p, c.j);
-                middle<S + 1>(lds, v, c, a);
-            } else {
-                store_last<S>(lds, v, c, a);
-            }
+    __device__ __forceinline__ static void stages(float2* lds, float2* v, const Ctx& c, const PassArgs& a,
+                                                  const float2* tw) {
+        butterflies<S>(v, c.j, tw);
+        if constexpr (S + 1 < NS) {
+            float2 w[maxv()];
+            exchange<S>(lds, v, w, c.p, c.j, S > 0);
+            stages<S + 1>(lds, w, c, a, tw);
+        } else {
+            store_last<S>(lds, v, c, a);
         }
     }
 
-    __device__ __forceinline__ static void run(const PassArgs& a, float2* lds) {
+    __device__ __forceinline__ static int64_t num_tiles(const PassArgs& a) {
+        return STRIDED ? ((a.C + P - 1) / P) * a.O1 * a.O2 : (a.C + P - 1) / P;
+    }
+
+    // Thread context for tile t.
+    __device__ __forceinline__ static Ctx make_ctx(const PassArgs& a, int64_t t) {
         const int tid = threadIdx.x;
         Ctx c;
         if constexpr (STRIDED) {
             c.p = tid % P;
             c.j = tid / P;
             const int64_t ctiles = (a.C + P - 1) / P;
-            const int64_t t = blockIdx.x;
             const int64_t rest = t / ctiles;
             c.col = (t - rest * ctiles) * P + c.p;
             c.o1 = rest % a.O1;
@@ -416,41 +538,73 @@ struct PencilPass {
         } else {
             c.j = tid % T;
             c.p = tid / T;
-            c.col = (int64_t)blockIdx.x * P + c.p;
+            c.col = t * P + c.p;
             c.o1 = 0;
             c.valid = c.col < a.C;
             c.base_in = c.col * a.os1_in;
             c.base_out = c.col * a.os1_out;
         }
-        const int64_t es = STRIDED ? a.es_in : 1;
+        return c;
+    }
 
-        float2 v[maxv()];
-        {   // first stage straight from HBM
-            using Q = St<0>;
+    static constexpr int V0 = St<0>::NB * St<0>::R;   // first-stage inputs per thread
+
+    // First-stage inputs straight from HBM.
+    __device__ __forceinline__ static void load_first(float2* v, const Ctx& c, const PassArgs& a) {
+        using Q = St<0>;
+        const int64_t es = STRIDED ? a.es_in : 1;
 #pragma unroll
-            for (int t = 0; t < Q::NB; ++t) {
-                const int b = c.j + t * T;
-                if (Q::NB * T != Q::NBF && b >= Q::NBF) continue;
+        for (int t = 0; t < Q::NB; ++t) {
+            const int b = c.j + t * T;
+            if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
-                for (int r = 0; r < Q::R; ++r)
-                    v[t * Q::R + r] = c.valid ? IO::load(a.src, c.base_in + (int64_t)(b + r * Q::NBF) * es)
-                                              : make_float2(0.f, 0.f);
-            }
+            for (int r = 0; r < Q::R; ++r)
+                v[t * Q::R + r] = c.valid ? gload(a.src, c.base_in + (int64_t)(b + r * Q::NBF) * es)
+                                          : make_float2(0.f, 0.f);
         }
-        butterflies<0>(v, c.j, a.tw);
-        if constexpr (NS == 1) {
-            store_last<0>(lds, v, c, a);
+    }
+
+    __device__ __forceinline__ static void run(const PassArgs& a, float2* lds) {
+        if constexpr (!PERSIST) {
+            const int64_t t = (FLAGS & kFlagXcdOrder) ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+            const Ctx c = make_ctx(a, t);
+            float2 v[maxv()];
+            load_first(v, c, a);
+            stages<0>(lds, v, c, a, a.tw);
         } else {
-            write_lds<0>(lds, v, c.p, c.j);
-            middle<1>(lds, v, c, a);
+            float2* twl = lds + LDS_ELEMS;
+            for (int i = threadIdx.x; i < N; i += T * P) twl[i] = a.tw[i];
+            const int64_t ntiles = num_tiles(a);
+            int64_t t = blockIdx.x;
+            float2 nxt[V0];
+            Ctx cn;
+            if (t < ntiles) {
+                cn = make_ctx(a, t);
+                load_first(nxt, cn, a);
+            }
+            __syncthreads();   // twiddle table visible
+            while (t < ntiles) {
+                const Ctx c = cn;
+                float2 v[maxv()];
+#pragma unroll
+                for (int i = 0; i < V0; ++i) v[i] = nxt[i];
+                const int64_t tn = t + gridDim.x;
+                if (tn < ntiles) {   // prefetch the next tile
+                    cn = make_ctx(a, tn);
+                    load_first(nxt, cn, a);
+                }
+                stages<0>(lds, v, c, a, twl);
+                __syncthreads();     // LDS free for the next tile
+                t = tn;
+            }
         }
     }
 };
 
-template <int N, int T, int P, bool STRIDED, class IO, int SIGN>
+template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1>
 __global__ __launch_bounds__(T * P) void pencil_pass_kernel(PassArgs a) {
     extern __shared__ float2 lds_dyn[];
-    PencilPass<N, T, P, STRIDED, IO, SIGN>::run(a, lds_dyn);
+    PencilPass<N, T, P, STRIDED, IO, SIGN, FLAGS, K>::run(a, lds_dyn);
 }
 
 }  // namespace wsfft

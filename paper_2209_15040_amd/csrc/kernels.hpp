@@ -10,6 +10,7 @@ enum StorageKind { kC64 = 0, kF16 = 1, kBF16 = 2 };
 struct PassKernel {
     int n;              // pencil length
     bool strided;       // layout: columns unit-stride (true) or pencils contiguous
+    bool four_step;     // compiled with the split-axis first-pass features
     int threads;        // workgroup size
     int per_block;      // pencils (contiguous) or columns (strided) per workgroup
     int lds_bytes;      // dynamic LDS per workgroup
@@ -18,9 +19,9 @@ struct PassKernel {
 };
 
 // NULL when no kernel of that length/layout exists.
-const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided);
+const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided, bool four_step);
 
-#define WSFFT_DECLARE_FIND(NAME) const PassKernel* NAME(int n, bool strided);
+#define WSFFT_DECLARE_FIND(NAME) const PassKernel* NAME(int n, bool strided, bool four_step);
 WSFFT_DECLARE_FIND(find_pass_c64_neg)
 WSFFT_DECLARE_FIND(find_pass_c64_pos)
 WSFFT_DECLARE_FIND(find_pass_f16_neg)

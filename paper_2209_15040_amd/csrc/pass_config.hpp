@@ -1,43 +1,78 @@
-// Launch geometry of the pencil passes: threads per pencil (T) and pencils
-// (contiguous layout) or columns (strided layout) per workgroup (P).
+// Launch geometry of the pencil passes.
+//
+//   T  threads per pencil          P  pencils (contiguous layout) or
+//   K  LDS exchange rounds            columns (strided layout) per workgroup
+//
+// Rules measured on MI355X at N = 512 (512^3 complex64):
+// * strided tiles need rows of >= 256 bytes (32 complex64 columns, 64 of
+//   the 4-byte types): 128-byte rows run the 2 MiB-stride pass at ~44% of
+//   the copy rate of 256-byte rows;
+// * 32 elements per thread with the exchange split into rounds of <= ~34 KB
+//   keeps two or more workgroups resident per CU, so one workgroup's
+//   transform and store drain overlap another's loads;
+// * contiguous pencils run best with 16 elements per thread and 256-thread
+//   workgroups;
+// * non-temporal (streaming) loads and stores help every pass.
 #pragma once
 #include "fft_device.hpp"
 
 namespace wsfft {
 
 constexpr int kLdsBytesMax = 160 * 1024;   // LDS per CU on gfx950
+constexpr int kLdsRoundBudget = 36 * 1024; // target LDS per strided workgroup
+constexpr int kPassFlags = kFlagNontemporal;
 
 constexpr int cfg_T_contig(int N) {
-    const int t = N / max_radix(make_radices(N));
-    return t < 1 ? 1 : (t > 1024 ? 1024 : t);
+    int t = N / 16;
+    if (t < 1) t = 1;
+    // every thread must own at least one butterfly of the widest stage
+    const int tmax = N / max_radix(make_radices(N));
+    if (tmax >= 1 && t > tmax) t = tmax;
+    return t > 1024 ? 1024 : t;
 }
 constexpr int cfg_P_contig(int N) {
     const int p = 256 / cfg_T_contig(N);
     return p < 1 ? 1 : p;
 }
 
-// Strided tiles want row segments of at least 128 bytes in storage:
-// 16 columns of complex64, 32 columns of 4-byte complex.
-constexpr int cfg_P_strided(int N, int bytes) {
-    int p = bytes == 8 ? 16 : 32;
-    const int t = N / max_radix(make_radices(N));
-    if (t > 0 && t * p < 256) {            // small N: widen the tile
-        const int want = 256 / t;
-        p = want > 64 ? 64 : want;
-    }
-    while (p > 1 && N * (p + 1) * 8 > kLdsBytesMax) p /= 2;
+constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+constexpr int pow2_floor(int n) {
+    int p = 1;
+    while (p * 2 <= n) p *= 2;
     return p;
 }
+
+// Elements per thread in the strided layout: 32 for powers of two; radix-3
+// stages leave some threads idle, so fewer there to stay within registers.
 constexpr int cfg_T_strided(int N, int bytes) {
+    (void)bytes;
+    const int e = is_pow2(N) ? 32 : 24;
+    int t = (N + e - 1) / e;
+    const int tmax = N / max_radix(make_radices(N));
+    if (tmax >= 1 && t > tmax) t = tmax;
+    return t < 1 ? 1 : t;
+}
+constexpr int cfg_P_strided(int N, int bytes) {
+    int p = bytes == 8 ? 32 : 64;
+    if (N <= 64) p = 64;                   // one full wave of columns at least
+    const int cap = pow2_floor(1024 / cfg_T_strided(N, bytes));
+    return p > cap ? cap : p;
+}
+// Smallest K dividing N whose exchange round fits the LDS budget; when that
+// takes more than 8 rounds, accept up to twice the budget instead.
+constexpr int cfg_K_strided(int N, int bytes) {
     const int p = cfg_P_strided(N, bytes);
-    int t = N / max_radix(make_radices(N));
-    if (t < 1) t = 1;
-    const int cap = 1024 / p;
-    return t > cap ? cap : t;
+    int first = 0;
+    for (int k = 1; k <= N && !first; ++k)
+        if (N % k == 0 && (N / k) * (p + 1) * 8 <= kLdsRoundBudget) first = k;
+    if (first && first <= 8) return first;
+    for (int k = 1; k <= N; ++k)
+        if (N % k == 0 && (N / k) * (p + 1) * 8 <= 2 * kLdsRoundBudget) return k;
+    return first ? first : N;
 }
 
-// Longest pencil a single pass handles in each layout (LDS capacity).
-constexpr int kMaxContigN = 16384;
+// Longest pencil a single pass handles in each layout.
+constexpr int kMaxContigN = 16384;   // one pencil of 16384 complex in LDS
 constexpr int kMaxStridedN = 1024;
 
 }  // namespace wsfft

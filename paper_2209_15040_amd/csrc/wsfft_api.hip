@@ -335,8 +335,8 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
 
     // kernels
     for (Pass& P : plan->passes) {
-        P.kern_neg = find_pass_kernel(kind, -1, (int)P.n, P.strided);
-        P.kern_pos = find_pass_kernel(kind, +1, (int)P.n, P.strided);
+        P.kern_neg = find_pass_kernel(kind, -1, (int)P.n, P.strided, P.four_step == 1);
+        P.kern_pos = find_pass_kernel(kind, +1, (int)P.n, P.strided, P.four_step == 1);
         if (!P.kern_neg || !P.kern_pos) { delete plan; return fail(WSFFT_ERROR_UNSUPPORTED_SIZE); }
         // one grid dimension holds at most 2^32 - 1 work-items
         const int64_t blocks = blocks_for(P, P.kern_neg);
@@ -608,11 +608,12 @@ wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const
 
 namespace wsfft {
 
-const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided) {
+const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided, bool four_step) {
     switch (kind) {
-        case kC64: return sign < 0 ? find_pass_c64_neg(n, strided) : find_pass_c64_pos(n, strided);
-        case kF16: return sign < 0 ? find_pass_f16_neg(n, strided) : find_pass_f16_pos(n, strided);
-        case kBF16: return sign < 0 ? find_pass_bf16_neg(n, strided) : find_pass_bf16_pos(n, strided);
+        case kC64: return sign < 0 ? find_pass_c64_neg(n, strided, four_step) : find_pass_c64_pos(n, strided, four_step);
+        case kF16: return sign < 0 ? find_pass_f16_neg(n, strided, four_step) : find_pass_f16_pos(n, strided, four_step);
+        case kBF16:
+            return sign < 0 ? find_pass_bf16_neg(n, strided, four_step) : find_pass_bf16_pos(n, strided, four_step);
     }
     return nullptr;
 }

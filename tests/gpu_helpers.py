@@ -17,7 +17,7 @@ def to_dev(a: np.ndarray) -> torch.Tensor:
 
 def to_host(t: torch.Tensor) -> np.ndarray:
     torch.cuda.synchronize()
-    return t.cpu().numpy()
+    return t.detach().cpu().numpy()
 
 
 def rel_l2(a, b) -> float:

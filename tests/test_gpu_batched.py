@@ -1,0 +1,110 @@
+"""wsfft_execute_batched: many transforms in one call, each checked element by
+element against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import need_gpu, rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ws():
+    return need_gpu()
+
+
+def test_96_uneven_arrays(ws):
+    """96 non-cubic arrays, each axis from {32, 64, 96, 128, 256}, U[-1,1), seed 3."""
+    shapes = synth.batched_shapes(96, seed=3)
+    arrays = synth.batched_arrays(shapes, seed=3)
+    plans = [ws.Plan(nx, ny, nz, "c64", -1) for nx, ny, nz in shapes]
+    xs = [to_dev(a) for a in arrays]
+    ys = [torch.empty_like(x) for x in xs]
+    ws.execute_batched(plans, xs, ys)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for a, y in zip(arrays, ys):
+        e = rel_l2(y.cpu().numpy(), oracle.fftn(a.astype(np.complex64).astype(np.complex128), -1))
+        worst = max(worst, e)
+    print(f"96 arrays, {sum(a.size for a in arrays)} elements, worst rel_l2 {worst:.3e}")
+    assert worst <= TOL
+
+
+def test_batched_adjoint_matches_single_calls(ws):
+    shapes = [(32, 64, 96), (96, 32, 32), (128, 32, 64), (64, 96, 32)]
+    plans = [ws.Plan(*s, "c64", -1) for s in shapes]
+    xs = [to_dev(synth.uniform_c((s[2], s[1], s[0]), seed=i)) for i, s in enumerate(shapes)]
+    ys = [torch.empty_like(x) for x in xs]
+    ws.execute_batched(plans, xs, ys, adjoint=True)
+    for p, x, y in zip(plans, xs, ys):
+        single = p.execute_adjoint(x)
+        torch.cuda.synchronize()
+        assert torch.equal(single, y)
+
+
+def test_uniform_batch_is_one_array_per_entry(ws):
+    """Same plan, buffers one array apart: the single-launch path."""
+    n, count = 4096, 64
+    a = synth.normal_c((count, n), seed=5).astype(np.complex64)
+    x = to_dev(a)
+    y = torch.empty_like(x)
+    p = ws.Plan(n, 1, 1, "c64", -1)
+    ws.execute_batched([p] * count, list(x), list(y))
+    assert rel_l2(to_host(y), oracle.fft1d_batch(a.astype(np.complex128), -1)) <= TOL
+
+
+def test_batch_of_3d_plans_uniform(ws):
+    shape = (32, 48, 64)
+    count = 5
+    a = synth.uniform_c((count * 64, 48, 32), seed=6).astype(np.complex64)
+    x = to_dev(a)
+    y = torch.empty_like(x)
+    p = ws.Plan(*shape, "c64", +1)
+    xs, ys = list(x.view(count, -1)), list(y.view(count, -1))
+    ws.execute_batched([p] * count, xs, ys)
+    yh = to_host(y).reshape(count, 64, 48, 32)
+    for i in range(count):
+        ref = oracle.fftn(a.reshape(count, 64, 48, 32)[i].astype(np.complex128), +1)
+        assert rel_l2(yh[i], ref) <= TOL
+
+
+def test_batched_rejects_mixed_dtypes(ws):
+    p1 = ws.Plan(32, 32, 1, "c64")
+    p2 = ws.Plan(32, 32, 1, "fp16")
+    x1 = torch.zeros((32, 32), dtype=torch.complex64, device="cuda")
+    x2 = torch.zeros((32, 32, 2), dtype=torch.float16, device="cuda")
+    with pytest.raises(ws.WsfftError) as ei:
+        ws.execute_batched([p1, p2], [x1, x2], [x1.clone(), x2.clone()])
+    assert ei.value.status == 1
+
+
+def test_graph_capture_replays(ws):
+    """The batched call captured into a HIP graph and replayed several times,
+    with eager work between replays, matches the eager result every time."""
+    shapes = [(64, 32, 96), (32, 96, 64), (96, 64, 32)]
+    plans = [ws.Plan(*s, "c64", -1) for s in shapes]
+    xs = [to_dev(synth.uniform_c((s[2], s[1], s[0]), seed=10 + i)) for i, s in enumerate(shapes)]
+    ys = [torch.empty_like(x) for x in xs]
+    ws.execute_batched(plans, xs, ys)
+    torch.cuda.synchronize()
+    eager = [y.clone() for y in ys]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for y in ys:
+            y.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            ws.execute_batched(plans, xs, ys, stream=s)
+    for rep in range(4):
+        for y in ys:
+            y.fill_(float(rep))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for y, e in zip(ys, eager):
+            assert torch.equal(y, e), f"replay {rep}"

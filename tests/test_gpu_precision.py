@@ -1,0 +1,90 @@
+"""16-bit storage (FP16, BF16) with FP32 arithmetic and per-pass power-of-two
+scaling, against the FP64 oracle applied to the same rounded input.
+
+Bound: relative L2 <= 3e-3 for the three-pass 512^3 workload.  Every stored
+pass rounds once to the storage type, and the transform is unitary up to
+scale, so the error grows like sqrt(passes) times the one-rounding floor; for
+schedules with more passes (split axes) the bound is scaled by
+sqrt(passes / 3).  Twiddles rounded to the storage type are the literal
+workload recipe; for BF16 that recipe's error sits above 3e-3 (the
+one-rounding floor of BF16 alone is ~1.7e-3), so it is reported and held to
+6e-3, while BF16 with FP32 twiddles is held to 3e-3.  Each test also prints
+the ratio to the single-rounding floor."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import c16_to_c128, c16_to_dev, need_gpu, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ws():
+    return need_gpu()
+
+
+def round_pairs(z, kind):
+    return synth.to_fp16_pairs(z) if kind == "fp16" else synth.to_bf16_pairs(z)
+
+
+def floor_error(X, S, kind):
+    """Error of rounding the exact scaled result once to the storage type."""
+    r = synth.pairs_to_c128(round_pairs(X * 2.0 ** -S, kind), kind) * 2.0 ** S
+    return rel_l2(r, X)
+
+
+def run_case(ws, shape, kind, flags, seed=2):
+    nx, ny, nz = shape
+    z = synth.normal_c((nz, ny, nx), seed=seed, scale=0.5)
+    pairs = round_pairs(z, kind)
+    a = synth.pairs_to_c128(pairs, kind)        # the exact stored input
+    p = ws.Plan(nx, ny, nz, kind, -1, flags)
+    y = p.execute(c16_to_dev(pairs, kind))
+    got = c16_to_c128(y, kind) * 2.0 ** p.scale_log2
+    X = oracle.fftn(a, -1)
+    return rel_l2(got, X), floor_error(X, p.scale_log2, kind), p
+
+
+CASES = [("fp16", 0, 3e-3), ("bf16", 0, 6e-3), ("bf16", 1, 3e-3)]
+
+
+@pytest.mark.parametrize("kind,flags,bound", CASES, ids=["fp16", "bf16", "bf16-fp32tw"])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (96, 32, 128), (32, 1, 1), (256, 256, 1), (8, 2048, 2)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_small(ws, shape, kind, flags, bound):
+    e, fl, p = run_case(ws, shape, kind, flags)
+    b = bound * max(1.0, (p.num_passes / 3) ** 0.5)
+    print(f"{kind} flags={flags} {shape}: rel_l2 {e:.3e}, floor {fl:.3e}, ratio {e / fl:.2f}, "
+          f"S={p.scale_log2}, passes {p.num_passes}, bound {b:.2e}")
+    assert e <= b
+
+
+@pytest.mark.parametrize("kind,flags,bound", CASES, ids=["fp16", "bf16", "bf16-fp32tw"])
+def test_512cubed(ws, kind, flags, bound):
+    """512^3 forward, re/im 0.5*N(0,1) seed 2 rounded to storage, every output
+    element against the oracle."""
+    e, fl, p = run_case(ws, (512, 512, 512), kind, flags)
+    print(f"512^3 {kind} flags={flags}: rel_l2 {e:.3e}, floor {fl:.3e}, ratio {e / fl:.2f}, S={p.scale_log2} "
+          f"[{p.describe()}]")
+    assert e <= bound
+
+
+def test_scale_log2_values(ws):
+    assert ws.Plan(512, 512, 512, "fp16").scale_log2 == 15      # 5 per 512-point pass
+    assert ws.Plan(96, 32, 256, "bf16").scale_log2 == 4 + 3 + 4
+    assert ws.Plan(512, 512, 512, "c64").scale_log2 == 0
+
+
+def test_constant_input_stays_finite(ws):
+    """A constant input puts all energy in one bin (N times larger): the
+    per-pass scaling keeps it in FP16 range."""
+    n = 256
+    pairs = np.zeros((n, n, n, 2), np.float16)
+    pairs[..., 0] = 1.0
+    p = ws.Plan(n, n, n, "fp16", -1)
+    y = c16_to_c128(p.execute(c16_to_dev(pairs, "fp16")), "fp16")
+    assert np.isfinite(y).all()
+    assert abs(y[0, 0, 0] * 2.0 ** p.scale_log2 - n ** 3) <= 1e-3 * n ** 3
