@@ -172,8 +172,7 @@ def variant_rank(ws, torch, shape, steps, warmup, batch=1):
     if batch == 1:
         ms, _ = time_events(lambda: plan.execute(x, y), steps, warmup)
     else:
-        xv, yv = list(x.view(batch, -1)), list(y.view(batch, -1))
-        ms, _ = time_events(lambda: ws.execute_batched([plan] * batch, xv, yv), steps, warmup)
+        ms, _ = time_events(lambda: ws.execute_many(plan, x, y, batch), steps, warmup)
     del x, y
     torch.cuda.empty_cache()
     return {"plan": plan.describe(), "ms": ms, "GFLOPs": batch * flops(N) / (ms * 1e-3) / 1e9,

@@ -212,6 +212,28 @@ def execute_batched(plans, ins, outs, adjoint: bool = False, stream=None) -> Non
     _check(_execute_batched(n, ph, ip, op, int(bool(adjoint)), _stream(stream)), "execute_batched")
 
 
+def execute_many(plan: Plan, x: torch.Tensor, out: torch.Tensor, count: int, adjoint: bool = False,
+                 stream=None) -> torch.Tensor:
+    """``wsfft_execute_batched`` over `count` arrays stored back to back in
+    `x` and `out` (one plan): the single-launch-per-pass batch."""
+    import numpy as np
+    per = 1 if plan.dtype == C64 else 2
+    for t, nm in ((x, "input"), (out, "output")):
+        if not t.is_cuda or t.dtype != _TORCH_DTYPE[plan.dtype] or not t.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous device tensor of the plan's dtype")
+        if t.numel() != plan.size * per * count:
+            raise ValueError(f"{nm} holds {t.numel()} elements, want {plan.size * per * count}")
+    span = plan.size * (8 if plan.dtype == C64 else 4)
+    offs = np.arange(count, dtype=np.uint64) * np.uint64(span)
+    ins = offs + np.uint64(x.data_ptr())
+    outs = offs + np.uint64(out.data_ptr())
+    hs = np.full(count, plan.handle, dtype=np.uint64)
+    P = ctypes.POINTER(_vp)
+    _check(_execute_batched(count, hs.ctypes.data_as(P), ins.ctypes.data_as(P), outs.ctypes.data_as(P),
+                            int(bool(adjoint)), _stream(stream)), "execute_batched")
+    return out
+
+
 # ---- plan cache and functional forms ------------------------------------------------
 
 _cache: dict = {}

@@ -287,6 +287,24 @@ struct PassArgs {
     float scale;          // multiplies every stored value
 };
 
+// One array of a merged batch launch: the fields of a direct pass that differ
+// between arrays sharing one kernel.  Tiles [previous tile_end, tile_end) of
+// the launch belong to this array.
+struct ArrayDesc {
+    const void* src;
+    void* dst;
+    int64_t C, O1, es, os1;
+    int64_t tile_end;
+    float scale;
+    int32_t pad;
+};
+constexpr int kMaxBatchDescs = 40;
+struct BatchTable {
+    int32_t count;      // 0: a single-array launch described by PassArgs alone
+    int32_t pad;
+    ArrayDesc d[kMaxBatchDescs];
+};
+
 // ------------------------------------------------------------ the kernel ---
 // N: pencil length.  T: threads per pencil.  P: pencils (contiguous layout)
 // or columns (strided layout) per workgroup.  K: the strided layout's LDS
@@ -564,14 +582,31 @@ struct PencilPass {
         }
     }
 
-    __device__ __forceinline__ static void run(const PassArgs& a, float2* lds) {
+    __device__ __forceinline__ static void run(const PassArgs& a0, const BatchTable& bt, float2* lds) {
         if constexpr (!PERSIST) {
-            const int64_t t = (FLAGS & kFlagXcdOrder) ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+            // A merged batch launch first picks its array; both kinds of
+            // launch then share one pipeline.
+            PassArgs a = a0;
+            int64_t t = (FLAGS & kFlagXcdOrder) ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+            if (bt.count != 0) {
+                int i = 0;
+                while (i + 1 < bt.count && t >= bt.d[i].tile_end) ++i;
+                const ArrayDesc& d = bt.d[i];
+                a.src = d.src;
+                a.dst = d.dst;
+                a.C = d.C;
+                a.O1 = d.O1;
+                a.es_in = a.es_out = d.es;
+                a.os1_in = a.os1_out = d.os1;
+                a.scale = d.scale;
+                t -= i ? bt.d[i - 1].tile_end : 0;
+            }
             const Ctx c = make_ctx(a, t);
             float2 v[maxv()];
             load_first(v, c, a);
             stages<0>(lds, v, c, a, a.tw);
         } else {
+            const PassArgs& a = a0;
             float2* twl = lds + LDS_ELEMS;
             for (int i = threadIdx.x; i < N; i += T * P) twl[i] = a.tw[i];
             const int64_t ntiles = num_tiles(a);
@@ -602,9 +637,9 @@ struct PencilPass {
 };
 
 template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1>
-__global__ __launch_bounds__(T * P) void pencil_pass_kernel(PassArgs a) {
+__global__ __launch_bounds__(T * P) void pencil_pass_kernel(PassArgs a, BatchTable bt) {
     extern __shared__ float2 lds_dyn[];
-    PencilPass<N, T, P, STRIDED, IO, SIGN, FLAGS, K>::run(a, lds_dyn);
+    PencilPass<N, T, P, STRIDED, IO, SIGN, FLAGS, K>::run(a, bt, lds_dyn);
 }
 
 }  // namespace wsfft

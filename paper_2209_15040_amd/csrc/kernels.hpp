@@ -14,7 +14,9 @@ struct PassKernel {
     int threads;        // workgroup size
     int per_block;      // pencils (contiguous) or columns (strided) per workgroup
     int lds_bytes;      // dynamic LDS per workgroup
-    hipError_t (*launch)(const PassArgs&, dim3 grid, hipStream_t);
+    // bt == nullptr: one array described by the PassArgs; otherwise a merged
+    // batch of direct passes (PassArgs supplies the shared fields)
+    hipError_t (*launch)(const PassArgs&, const BatchTable* bt, dim3 grid, hipStream_t);
     hipError_t (*prepare)();   // one-time function attributes
 };
 

@@ -520,7 +520,79 @@ bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out,
     }
     const int sign = mode == 0 ? plan->sign : -plan->sign;
     const PassKernel* k = sign < 0 ? P.kern_neg : P.kern_pos;
-    return k->launch(a, grid, stream) == hipSuccess;
+    return k->launch(a, nullptr, grid, stream) == hipSuccess;
+}
+
+// Pass `pi` of every entry of a batch.  Direct passes that share a kernel and
+// a twiddle precision go out as merged launches of up to kMaxBatchDescs
+// arrays (one BatchTable each); split-axis passes launch one by one.
+bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const* in, void* const* out,
+                         int mode, size_t pi, hipStream_t stream) {
+    struct Group {
+        const PassKernel* k;
+        unsigned twbits;
+        std::vector<int> idx;
+    };
+    std::vector<Group> groups;
+    for (int i = 0; i < count; ++i) {
+        const wsfft_plan_s* p = plans[i];
+        if (pi >= p->passes.size()) continue;
+        const Pass& P = p->passes[pi];
+        if (P.four_step != 0) {
+            if (!launch_pass(p, pi, in[i], out[i], mode, stream)) return false;
+            continue;
+        }
+        const int sign = mode == 0 ? p->sign : -p->sign;
+        const PassKernel* k = sign < 0 ? P.kern_neg : P.kern_pos;
+        const unsigned twbits = (unsigned)p->dtype * 2u + (p->flags & WSFFT_FLAG_FP32_TWIDDLES ? 1u : 0u);
+        Group* g = nullptr;
+        for (Group& q : groups)
+            if (q.k == k && q.twbits == twbits) g = &q;
+        if (!g) {
+            groups.push_back({k, twbits, {}});
+            g = &groups.back();
+        }
+        g->idx.push_back(i);
+    }
+    for (const Group& g : groups) {
+        for (size_t c0 = 0; c0 < g.idx.size(); c0 += kMaxBatchDescs) {
+            const size_t c1 = std::min(g.idx.size(), c0 + (size_t)kMaxBatchDescs);
+            if (c1 - c0 == 1) {
+                const int i = g.idx[c0];
+                if (!launch_pass(plans[i], pi, in[i], out[i], mode, stream)) return false;
+                continue;
+            }
+            BatchTable bt{};
+            bt.count = (int32_t)(c1 - c0);
+            int64_t tiles = 0;
+            PassArgs shared{};
+            for (size_t e = c0; e < c1; ++e) {
+                const int i = g.idx[e];
+                const wsfft_plan_s* p = plans[i];
+                const Pass& P = p->passes[pi];
+                const bool ip = in[i] == out[i];
+                auto sel = [&](int s) -> void* {
+                    return s == 0 ? const_cast<void*>(in[i]) : (s == 1 ? out[i] : p->work);
+                };
+                ArrayDesc& d = bt.d[e - c0];
+                d.src = sel(ip ? P.src_sel_ip : P.src_sel);
+                d.dst = sel(ip ? P.dst_sel_ip : P.dst_sel);
+                d.C = P.args.C;
+                d.O1 = P.args.O1;
+                d.es = P.args.es_in;
+                d.os1 = P.args.os1_in;
+                d.scale = P.pass_scale;
+                if (mode == 2 && pi + 1 == p->passes.size())
+                    d.scale = (float)((double)P.pass_scale / ((double)p->n[0] * (double)p->n[1] * (double)p->n[2]));
+                tiles += blocks_for(P, g.k);
+                d.tile_end = tiles;
+                if (e == c0) shared = P.args;
+            }
+            if (tiles * g.k->threads > 0xffffffffLL) return false;
+            if (g.k->launch(shared, &bt, dim3((unsigned)tiles), stream) != hipSuccess) return false;
+        }
+    }
+    return true;
 }
 
 wsfft_status_t exec_plan(const wsfft_plan_s* plan, const void* in, void* out, int mode, hipStream_t stream) {
@@ -598,9 +670,7 @@ wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const
             if (st != WSFFT_SUCCESS) return st;
         }
     for (size_t pi = 0; pi < maxp; ++pi)
-        for (int i = 0; i < count; ++i)
-            if (pi < plans[i]->passes.size() && !launch_pass(plans[i], pi, in[i], out[i], mode, stream))
-                return WSFFT_ERROR_HIP;
+        if (!launch_level_merged(count, plans, in, out, mode, pi, stream)) return WSFFT_ERROR_HIP;
     return WSFFT_SUCCESS;
 }
 

@@ -178,7 +178,7 @@ def test_1d_batch_65536(ws):
     p = ws.Plan(n, 1, 1, "c64", -1)
     x = torch.from_numpy(a).cuda()
     y = torch.empty_like(x)
-    ws.execute_batched([p] * count, list(x), list(y))
+    ws.execute_many(p, x, y, count)
     yh = to_host(y)
     sel = np.arange(0, count, 64)
     ref = oracle.fft1d_batch(a[sel].astype(np.complex128), -1)
