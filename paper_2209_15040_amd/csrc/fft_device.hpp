@@ -177,6 +177,7 @@ constexpr int stage_ns(const Radices& R, int s) {
 
 // --------------------------------------------------------- storage types ---
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct IoC64 {   // complex64: FP32 re, FP32 im
     static constexpr int bytes = 8;
@@ -190,6 +191,17 @@ struct IoC64 {   // complex64: FP32 re, FP32 im
     static __device__ __forceinline__ float2 load_nt(const void* p, int64_t i) {
         const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p) + i);
         return make_float2(v.x, v.y);
+    }
+    // elements i and i+1 in one access (i even, 16-byte aligned)
+    static __device__ __forceinline__ void load2_nt(const void* p, int64_t i, float2& a, float2& b) {
+        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + i / 2);
+        a = make_float2(v.x, v.y);
+        b = make_float2(v.z, v.w);
+    }
+    static __device__ __forceinline__ void store2_nt(void* p, int64_t i, float2 a, float2 b) {
+        f32x4 w;
+        w.x = a.x; w.y = a.y; w.z = b.x; w.w = b.y;
+        __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p) + i / 2);
     }
     static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
         f32x2 w;
@@ -215,6 +227,17 @@ struct IoF16 {   // FP16 re, FP16 im
     static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
         __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, __float22half2_rn(v)),
                                     reinterpret_cast<uint32_t*>(p) + i);
+    }
+    // pairs move as one 64-bit scalar access
+    static __device__ __forceinline__ void load2_nt(const void* p, int64_t i, float2& a, float2& b) {
+        const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(p) + i / 2);
+        a = __half22float2(__builtin_bit_cast(__half2, (uint32_t)w));
+        b = __half22float2(__builtin_bit_cast(__half2, (uint32_t)(w >> 32)));
+    }
+    static __device__ __forceinline__ void store2_nt(void* p, int64_t i, float2 a, float2 b) {
+        const uint64_t w = (uint64_t)__builtin_bit_cast(uint32_t, __float22half2_rn(a)) |
+                           ((uint64_t)__builtin_bit_cast(uint32_t, __float22half2_rn(b)) << 32);
+        __builtin_nontemporal_store(w, reinterpret_cast<uint64_t*>(p) + i / 2);
     }
 };
 
@@ -242,6 +265,17 @@ struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
         __builtin_nontemporal_store(f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16),
                                     reinterpret_cast<uint32_t*>(p) + i);
     }
+    static __device__ __forceinline__ void load2_nt(const void* p, int64_t i, float2& a, float2& b) {
+        const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(p) + i / 2);
+        const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+        a = make_float2(__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u));
+        b = make_float2(__uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u));
+    }
+    static __device__ __forceinline__ void store2_nt(void* p, int64_t i, float2 a, float2 b) {
+        const uint64_t w = (uint64_t)(f32_to_bf16_rne(a.x) | (f32_to_bf16_rne(a.y) << 16)) |
+                           ((uint64_t)(f32_to_bf16_rne(b.x) | (f32_to_bf16_rne(b.y) << 16)) << 32);
+        __builtin_nontemporal_store(w, reinterpret_cast<uint64_t*>(p) + i / 2);
+    }
 };
 
 // Kernel feature flags (template parameter FLAGS).
@@ -256,6 +290,10 @@ enum : int {
     kFlagFourStep = 8,      // first pass of a split axis: inter-pass twiddles
                             // and the transposed store (PassArgs tw4_mode,
                             // tstore) are compiled in only with this flag
+    kFlagPairs = 16,        // contiguous layout: thread j owns butterflies
+                            // j*NB .. j*NB+NB-1 of every stage, so its first
+                            // loads and last stores come in adjacent pairs that
+                            // move as one wider access
 };
 
 // Workgroup id -> tile id such that each XCD gets one contiguous range of
@@ -328,11 +366,14 @@ struct PencilPass {
     static constexpr Radices RD = make_radices(N);
     static constexpr int NS = RD.n;
     static constexpr int ROWS = N / K;   // LDS rows per exchange round
-    // LDS layout: strided tiles store [element][column], contiguous tiles
-    // [pencil][element]; one float2 of padding per row breaks power-of-two
-    // bank strides.
-    static constexpr int LDS_ROW = STRIDED ? (P + 1) : (N + 1);
-    static constexpr int LDS_ELEMS = STRIDED ? ROWS * (P + 1) : P * (N + 1);
+    // LDS layout: strided tiles store [element][column] with one float2 of
+    // padding per row; contiguous tiles store [pencil][element] with one
+    // float2 of padding after every 2^PADSH elements, which spreads the
+    // radix-stride writes of the first stages over all banks.
+    static constexpr bool PAIRS = !STRIDED && (FLAGS & kFlagPairs) != 0;
+    static constexpr int PADSH = PAIRS ? 4 : 3;
+    static constexpr int LDS_ROW = STRIDED ? (P + 1) : (N + (N >> PADSH) + 1);
+    static constexpr int LDS_ELEMS = STRIDED ? ROWS * (P + 1) : P * LDS_ROW;
     static constexpr int lds_bytes() { return (LDS_ELEMS + (PERSIST ? N : 0)) * 8; }
     static constexpr int threads() { return T * P; }
 
@@ -343,6 +384,8 @@ struct PencilPass {
         static constexpr int NB = (NBF + T - 1) / T;    // per thread
         static constexpr int TWS = N / (Ns * R);        // twiddle table stride
         static constexpr bool FULL = NB * T == NBF;     // every thread busy
+        // butterfly of thread j's slot t
+        static constexpr __host__ __device__ int bf(int j, int t) { return PAIRS ? j * NB + t : j + t * T; }
     };
 
     static constexpr int maxv() {
@@ -356,8 +399,45 @@ struct PencilPass {
     }
 
     __device__ __forceinline__ static int lidx(int p, int e) {
-        return STRIDED ? e * LDS_ROW + p : p * LDS_ROW + e;
+        return STRIDED ? e * LDS_ROW + p : p * LDS_ROW + e + (e >> PADSH);
     }
+
+    // Exchange round of the value in slot (t, r) when written after stage S
+    // (W) or read before stage S+1 (R): the round if it is the same for every
+    // thread j, else -1 (decided at run time).  Tables are built at compile
+    // time, so after unrolling each access is either kept in exactly one
+    // round or decided by one compare.
+    template <int S> struct Rounds {
+        int w[St<S>::NB][St<S>::R];
+        int r[St<S + 1>::NB][St<S + 1>::R];
+        constexpr Rounds() : w(), r() {
+            using Q = St<S>;
+            using Q2 = St<S + 1>;
+            for (int t = 0; t < Q::NB; ++t)
+                for (int rr = 0; rr < Q::R; ++rr) {
+                    int h = -2;
+                    for (int j = 0; j < T; ++j) {
+                        const int b = Q::bf(j, t);
+                        if (!Q::FULL && b >= Q::NBF) continue;
+                        const int e = (b / Q::Ns) * Q::Ns * Q::R + b % Q::Ns + rr * Q::Ns;
+                        const int hh = e / ROWS;
+                        h = (h == -2 || h == hh) ? hh : -1;
+                    }
+                    w[t][rr] = h;
+                }
+            for (int t = 0; t < Q2::NB; ++t)
+                for (int rr = 0; rr < Q2::R; ++rr) {
+                    int h = -2;
+                    for (int j = 0; j < T; ++j) {
+                        const int b = Q2::bf(j, t);
+                        if (!Q2::FULL && b >= Q2::NBF) continue;
+                        const int hh = (b + rr * Q2::NBF) / ROWS;
+                        h = (h == -2 || h == hh) ? hh : -1;
+                    }
+                    r[t][rr] = h;
+                }
+        }
+    };
 
     struct Ctx {
         int p, j;
@@ -372,7 +452,7 @@ struct PencilPass {
         using Q = St<S>;
 #pragma unroll
         for (int t = 0; t < Q::NB; ++t) {
-            const int b = j + t * T;
+            const int b = Q::bf(j, t);
             if (!Q::FULL && b >= Q::NBF) continue;
             float2* u = v + t * Q::R;
             if (S > 0) {
@@ -395,29 +475,34 @@ struct PencilPass {
                                                     bool lead) {
         using Q = St<S>;
         using Q2 = St<S + 1>;
+        constexpr Rounds<S> RT{};
 #pragma unroll
         for (int h = 0; h < K; ++h) {
             if (lead || h > 0) __syncthreads();
 #pragma unroll
             for (int t = 0; t < Q::NB; ++t) {
-                const int b = j + t * T;
+                const int b = Q::bf(j, t);
                 if (!Q::FULL && b >= Q::NBF) continue;
                 const int o = (b / Q::Ns) * Q::Ns * Q::R + b % Q::Ns;
 #pragma unroll
                 for (int r = 0; r < Q::R; ++r) {
                     const int e = o + r * Q::Ns;
-                    if (K == 1 || e / ROWS == h) lds[lidx(p, e - h * ROWS)] = vo[t * Q::R + r];
+                    const int hs = RT.w[t][r];
+                    if (K == 1 || hs == h || (hs < 0 && e / ROWS == h))
+                        lds[lidx(p, e - h * ROWS)] = vo[t * Q::R + r];
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < Q2::NB; ++t) {
-                const int b = j + t * T;
+                const int b = Q2::bf(j, t);
                 if (!Q2::FULL && b >= Q2::NBF) continue;
 #pragma unroll
                 for (int r = 0; r < Q2::R; ++r) {
                     const int e = b + r * Q2::NBF;
-                    if (K == 1 || e / ROWS == h) vi[t * Q2::R + r] = lds[lidx(p, e - h * ROWS)];
+                    const int hs = RT.r[t][r];
+                    if (K == 1 || hs == h || (hs < 0 && e / ROWS == h))
+                        vi[t * Q2::R + r] = lds[lidx(p, e - h * ROWS)];
                 }
             }
         }
@@ -446,7 +531,7 @@ struct PencilPass {
                 __syncthreads();
 #pragma unroll
                 for (int t = 0; t < Q::NB; ++t) {
-                    const int b = c.j + t * T;
+                    const int b = Q::bf(c.j, t);
                     if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
                     for (int r = 0; r < Q::R; ++r) {
@@ -489,7 +574,7 @@ struct PencilPass {
             float2 w4[Q::NB * Q::R];
 #pragma unroll
             for (int t = 0; t < Q::NB; ++t) {
-                const int b = c.j + t * T;
+                const int b = Q::bf(c.j, t);
 #pragma unroll
                 for (int r = 0; r < Q::R; ++r)
                     w4[t * Q::R + r] = (Q::FULL || b < Q::NBF) ? tw4_of(b + r * Q::NBF, c.col, c.o1, a)
@@ -497,7 +582,7 @@ struct PencilPass {
             }
 #pragma unroll
             for (int t = 0; t < Q::NB; ++t) {
-                const int b = c.j + t * T;
+                const int b = Q::bf(c.j, t);
                 if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
                 for (int r = 0; r < Q::R; ++r) {
@@ -508,9 +593,22 @@ struct PencilPass {
             }
             return;
         }
+        if constexpr (pairable<S>()) {
+            if (pair_aligned(a.dst, c.base_out)) {
+#pragma unroll
+                for (int t = 0; t < Q::NB; t += 2) {
+                    const int b = Q::bf(c.j, t);
+#pragma unroll
+                    for (int r = 0; r < Q::R; ++r)
+                        IO::store2_nt(a.dst, c.base_out + b + r * Q::NBF, cscale(v[t * Q::R + r], a.scale),
+                                      cscale(v[(t + 1) * Q::R + r], a.scale));
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int t = 0; t < Q::NB; ++t) {
-            const int b = c.j + t * T;
+            const int b = Q::bf(c.j, t);
             if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
             for (int r = 0; r < Q::R; ++r) {
@@ -568,12 +666,32 @@ struct PencilPass {
     static constexpr int V0 = St<0>::NB * St<0>::R;   // first-stage inputs per thread
 
     // First-stage inputs straight from HBM.
+    // Paired accesses: thread slots t and t+1 hold adjacent elements.
+    template <int S> static constexpr bool pairable() {
+        return PAIRS && NT && St<S>::FULL && St<S>::NB % 2 == 0 && St<S>::NBF % 2 == 0;
+    }
+    __device__ __forceinline__ static bool pair_aligned(const void* p, int64_t base) {
+        return ((reinterpret_cast<uintptr_t>(p) & (2 * IO::bytes - 1)) == 0) && (base % 2 == 0);
+    }
+
     __device__ __forceinline__ static void load_first(float2* v, const Ctx& c, const PassArgs& a) {
         using Q = St<0>;
+        if constexpr (pairable<0>()) {
+            if (c.valid && pair_aligned(a.src, c.base_in)) {
+#pragma unroll
+                for (int t = 0; t < Q::NB; t += 2) {
+                    const int b = Q::bf(c.j, t);
+#pragma unroll
+                    for (int r = 0; r < Q::R; ++r)
+                        IO::load2_nt(a.src, c.base_in + b + r * Q::NBF, v[t * Q::R + r], v[(t + 1) * Q::R + r]);
+                }
+                return;
+            }
+        }
         const int64_t es = STRIDED ? a.es_in : 1;
 #pragma unroll
         for (int t = 0; t < Q::NB; ++t) {
-            const int b = c.j + t * T;
+            const int b = Q::bf(c.j, t);
             if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
             for (int r = 0; r < Q::R; ++r)
