@@ -151,12 +151,19 @@ def variant_batched(ws, torch, steps, warmup):
     fl = sum(flops(nx * ny * nz) for nx, ny, nz in shapes)
     ms, _ = time_events(lambda: ws.execute_batched(plans, xs, ys), steps, warmup)
     ms_loop, _ = time_events(lambda: [p.execute(a, b) for p, a, b in zip(plans, xs, ys)], steps, warmup)
+    bp = ws.BatchPlan(plans, xs, ys)
+    ms_persist, _ = time_events(bp.execute, steps, warmup)
+    timed_out = bp.timed_out()
+    tiles = bp.tiles
+    bp.close()
     byts = sum(2 * 8 * nx * ny * nz * sum(d > 1 for d in (nx, ny, nz)) for nx, ny, nz in shapes)
     del xs, ys
     torch.cuda.empty_cache()
     return {"arrays": len(shapes), "elements": tot, "GiB_in_plus_out": 2 * 8 * tot / 2 ** 30,
-            "ms_batched": ms, "ms_loop_of_plans": ms_loop, "GFLOPs": fl / (ms * 1e-3) / 1e9,
-            "hbm_frac": byts / (ms * 1e-3) / HBM_PEAK}
+            "ms_batched": ms, "ms_loop_of_plans": ms_loop, "ms_one_persistent_launch": ms_persist,
+            "persistent_tiles": tiles, "persistent_timed_out": timed_out,
+            "GFLOPs": fl / (min(ms, ms_persist) * 1e-3) / 1e9,
+            "hbm_frac": byts / (min(ms, ms_persist) * 1e-3) / HBM_PEAK}
 
 
 def variant_rank(ws, torch, shape, steps, warmup, batch=1):

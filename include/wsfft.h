@@ -82,6 +82,20 @@ typedef enum {
 
 /* Plan flags for wsfft_plan_create_ex. */
 #define WSFFT_FLAG_FP32_TWIDDLES 1u   /* 16-bit plans: keep twiddles in FP32 */
+#define WSFFT_FLAG_TUNE 2u            /* time each pass's kernel variants at creation */
+
+/*
+ * Autotuning.  Passes of the hot lengths (powers of two up to 1024 strided,
+ * 4096 contiguous) have several compiled launch variants (radix schedule,
+ * tile width).  Plan creation picks, per pass geometry, the variant recorded
+ * in the tuning cache ($WSFFT_TUNE_CACHE, else $HOME/.cache/wsfft_tune.txt);
+ * with WSFFT_FLAG_TUNE or the environment WSFFT_TUNE=1 it times every
+ * variant of uncached geometries with HIP events on two temporary device
+ * buffers of one array each (allocated and freed inside plan creation) and
+ * appends the winner to the cache.  WSFFT_TUNE=0 disables both, and the
+ * diagnostic WSFFT_TUNE_FORCE=<v> selects variant v wherever it exists.
+ * Execution is unaffected: the chosen kernels are fixed in the plan.
+ */
 
 /*
  * Create a plan for an nx x ny x nz transform of the given storage type with
@@ -138,6 +152,34 @@ wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const
  * and profiling. */
 wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const void* in, void* out,
                                   hipStream_t stream);
+
+/*
+ * Batch plans: a whole batch as ONE persistent kernel launch.
+ *
+ * wsfft_batch_plan_create binds `count` plans and their buffers (same
+ * meaning as wsfft_execute_batched; buffers must stay valid while the batch
+ * plan is used), checks every entry, uploads a table of the supersteps of all
+ * arrays and allocates the batch plan's own completion counters.
+ * wsfft_batch_execute then enqueues one launch of a resident grid that walks
+ * every tile of every pass of every array; a tile of superstep L of an array
+ * starts once all tiles of superstep L-1 of that array are done.  No host
+ * copies or allocations happen in execute, so it can be captured in a HIP
+ * graph.  A batch plan must not run concurrently with itself (its counters
+ * are shared by its launches).  Supported: WSFFT_C64 plans whose axes are 32,
+ * 64, 96, 128 or 256 long (or 1), one effective sign across the batch; other
+ * batches return WSFFT_ERROR_UNSUPPORTED_SIZE and should use
+ * wsfft_execute_batched.  Dependency waits are bounded: if one ever timed out,
+ * the results are invalid and wsfft_batch_plan_check reports it (it
+ * synchronises with the device).  NULL on error (wsfft_batch_get_last_error).
+ */
+typedef struct wsfft_batch_plan_s* wsfft_batch_plan_t;
+wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans, const void* const* in,
+                                           void* const* out, int adjoint);
+wsfft_status_t wsfft_batch_get_last_error(void);
+wsfft_status_t wsfft_batch_execute(wsfft_batch_plan_t batch, hipStream_t stream);
+int64_t wsfft_batch_plan_tiles(wsfft_batch_plan_t batch);      /* work items per execution; -1 invalid */
+wsfft_status_t wsfft_batch_plan_check(wsfft_batch_plan_t batch, int* timed_out);
+void wsfft_batch_plan_destroy(wsfft_batch_plan_t batch);
 
 /* S of the stored 2^-S scaling (0 for WSFFT_C64); -1 for an invalid plan. */
 int wsfft_plan_scale_log2(wsfft_plan_t plan);

@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libwsfft.so")
 
 C64, C16_FP16, C16_BF16 = 0, 1, 2
 FLAG_FP32_TWIDDLES = 1
+FLAG_TUNE = 2
 DTYPES = {"c64": C64, "fp16": C16_FP16, "bf16": C16_BF16}
 _TORCH_DTYPE = {C64: torch.complex64, C16_FP16: torch.float16, C16_BF16: torch.bfloat16}
 
@@ -72,6 +73,13 @@ _num_passes = _sig("wsfft_plan_num_passes", _int, [_vp])
 _work_bytes = _sig("wsfft_plan_work_bytes", _i64, [_vp])
 _describe = _sig("wsfft_plan_describe", _int, [_vp, ctypes.c_char_p, ctypes.c_size_t])
 _destroy = _sig("wsfft_plan_destroy", None, [_vp])
+_batch_create = _sig("wsfft_batch_plan_create", _vp,
+                     [_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _int])
+_batch_error = _sig("wsfft_batch_get_last_error", _int, [])
+_batch_execute = _sig("wsfft_batch_execute", _int, [_vp, _vp])
+_batch_tiles = _sig("wsfft_batch_plan_tiles", _i64, [_vp])
+_batch_check = _sig("wsfft_batch_plan_check", _int, [_vp, ctypes.POINTER(_int)])
+_batch_destroy = _sig("wsfft_batch_plan_destroy", None, [_vp])
 _real_to_complex = _sig("wsfft_real_to_complex", _int, [_vp, _vp, _i64, _vp])
 _complex_real_part = _sig("wsfft_complex_real_part", _int, [_vp, _vp, _i64, _vp])
 _poisson_symbol = _sig("wsfft_poisson_symbol", _int, [_vp, _i64, _i64, _i64, _vp])
@@ -232,6 +240,51 @@ def execute_many(plan: Plan, x: torch.Tensor, out: torch.Tensor, count: int, adj
     _check(_execute_batched(count, hs.ctypes.data_as(P), ins.ctypes.data_as(P), outs.ctypes.data_as(P),
                             int(bool(adjoint)), _stream(stream)), "execute_batched")
     return out
+
+
+class BatchPlan:
+    """``wsfft_batch_plan_create``: a batch bound to its buffers, executed as
+    one persistent launch by :meth:`execute`.  Keeps the plans and tensors
+    alive while it exists."""
+
+    def __init__(self, plans, ins, outs, adjoint: bool = False):
+        n = len(plans)
+        if len(ins) != n or len(outs) != n:
+            raise ValueError("plans, ins and outs must have one entry each")
+        for p, i, o in zip(plans, ins, outs):
+            p._check_tensor(i, "input")
+            p._check_tensor(o, "output")
+        arr = ctypes.c_void_p * max(n, 1)
+        h = _batch_create(n, arr(*[p.handle for p in plans]), arr(*[t.data_ptr() for t in ins]),
+                          arr(*[t.data_ptr() for t in outs]), int(bool(adjoint)))
+        if not h:
+            raise WsfftError(_batch_error(), "batch_plan_create")
+        self._h = h
+        self._keep = (list(plans), list(ins), list(outs))
+
+    @property
+    def tiles(self) -> int:
+        return _batch_tiles(self._h)
+
+    def execute(self, stream=None) -> None:
+        _check(_batch_execute(self._h, _stream(stream)), "batch_execute")
+
+    def timed_out(self) -> bool:
+        """True if a dependency wait ever timed out (synchronises)."""
+        flag = _int(0)
+        _check(_batch_check(self._h, ctypes.byref(flag)), "batch_plan_check")
+        return bool(flag.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- plan cache and functional forms ------------------------------------------------

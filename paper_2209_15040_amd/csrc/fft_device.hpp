@@ -98,44 +98,120 @@ template <int SIGN> struct Dft<8, SIGN> {
     }
 };
 
-// 16 = 4 x 4: X[k1 + 4 k2] = sum_n2 W4^(n2 k2) W16^(n2 k1) sum_n1 a[4 n1 + n2] W4^(n1 k1)
-template <int SIGN> struct Dft<16, SIGN> {
-    static __device__ __forceinline__ void run(float2* v) {
-        // W16^m = (cos(2 pi m/16), SIGN*sin(2 pi m/16)) for the m that occur
-        const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
-        const float c2 = 0.70710678118654752440f;
-        float2 y[4][4];
-#pragma unroll
-        for (int n2 = 0; n2 < 4; ++n2) {
-            float2 t[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
-            Dft<4, SIGN>::run(t);
-#pragma unroll
-            for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+// ------------------------------------------- compile-time roots of unity ---
+constexpr double kTwoPi = 6.28318530717958647692528676655900577;
+
+constexpr double taylor_sin(double x) {   // |x| <= pi/4
+    double term = x, sum = x;
+    for (int k = 1; k < 12; ++k) {
+        term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double taylor_cos(double x) {   // |x| <= pi/4
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 12; ++k) {
+        term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+struct CosSin {
+    double c, s;
+};
+// cos and sin of 2*pi*m/R, reduced to the first octant by exact symmetry.
+constexpr CosSin root_cs(int m, int R) {
+    m = ((m % R) + R) % R;
+    const int u = 4 * m, q = u / R, r = u % R;   // angle = (pi/2) * (q + r/R)
+    double c = 1.0, s = 0.0;
+    if (2 * r <= R) {
+        const double phi = (kTwoPi / 4.0) * r / R;
+        c = taylor_cos(phi);
+        s = taylor_sin(phi);
+    } else {
+        const double phi = (kTwoPi / 4.0) * (R - r) / R;
+        c = taylor_sin(phi);
+        s = taylor_cos(phi);
+    }
+    switch (q & 3) {
+        case 0: return {c, s};
+        case 1: return {-s, c};
+        case 2: return {-c, -s};
+        default: return {s, -c};
+    }
+}
+
+// a * W_R^M with W_R = exp(SIGN*2*pi*i/R); quarter turns are exact swaps,
+// eighth turns cost one multiply per component.
+template <int R, int M, int SIGN>
+__device__ __forceinline__ float2 twc(float2 a) {
+    constexpr int m = M % R;
+    if constexpr (m == 0) {
+        return a;
+    } else if constexpr ((4 * m) % R == 0) {
+        constexpr int q = 4 * m / R;
+        if constexpr (q == 1) return crot90<SIGN>(a);
+        else if constexpr (q == 2) return make_float2(-a.x, -a.y);
+        else return crot90<-SIGN>(a);
+    } else if constexpr ((8 * m) % R == 0) {
+        constexpr CosSin w = root_cs(m, R);
+        constexpr float h = 0.70710678118654752440f;
+        constexpr bool cp = w.c > 0, sp = (SIGN * w.s) > 0;   // signs of re, im of W
+        const float ax = a.x, ay = a.y;
+        const float re = (cp ? ax : -ax) - (sp ? ay : -ay);
+        const float im = (sp ? ax : -ax) + (cp ? ay : -ay);
+        return make_float2(h * re, h * im);
+    } else {
+        constexpr CosSin w = root_cs(m, R);
+        return cmul(a, make_float2((float)w.c, (float)(SIGN * w.s)));
+    }
+}
+
+// Composite R = R1*R2 DFT (Cooley-Tukey within registers):
+//   X[k1 + R1*k2] = sum_n2 W_R2^(n2 k2) W_R^(n2 k1) sum_n1 x[R2 n1 + n2] W_R1^(n1 k1)
+template <int R1, int R2, int SIGN> struct DftComp {
+    static constexpr int R = R1 * R2;
+    template <int I>
+    static __device__ __forceinline__ void twiddle(float2* y) {
+        if constexpr (I < R) {
+            constexpr int n2 = I / R1, k1 = I % R1;
+            y[I] = twc<R, n2 * k1, SIGN>(y[I]);
+            twiddle<I + 1>(y);
         }
-        const float sg = (float)SIGN;
-        const float2 w1 = make_float2(c1, sg * s1);     // m = 1
-        const float2 w2 = make_float2(c2, sg * c2);     // m = 2
-        const float2 w3 = make_float2(s1, sg * c1);     // m = 3
-        const float2 w6 = make_float2(-c2, sg * c2);    // m = 6
-        const float2 w9 = make_float2(-c1, -sg * s1);   // m = 9
-        y[1][1] = cmul(y[1][1], w1);
-        y[1][2] = cmul(y[1][2], w2);
-        y[1][3] = cmul(y[1][3], w3);
-        y[2][1] = cmul(y[2][1], w2);
-        y[2][2] = crot90<SIGN>(y[2][2]);                // m = 4
-        y[2][3] = cmul(y[2][3], w6);
-        y[3][1] = cmul(y[3][1], w3);
-        y[3][2] = cmul(y[3][2], w6);
-        y[3][3] = cmul(y[3][3], w9);
+    }
+    static __device__ __forceinline__ void run(float2* v) {
+        float2 y[R];
 #pragma unroll
-        for (int k1 = 0; k1 < 4; ++k1) {
-            float2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
-            Dft<4, SIGN>::run(t);
+        for (int n2 = 0; n2 < R2; ++n2) {
+            float2 u[R1];
 #pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+            for (int n1 = 0; n1 < R1; ++n1) u[n1] = v[R2 * n1 + n2];
+            Dft<R1, SIGN>::run(u);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = u[k1];
+        }
+        twiddle<0>(y);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            float2 w[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) w[n2] = y[n2 * R1 + k1];
+            Dft<R2, SIGN>::run(w);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = w[k2];
         }
     }
 };
+
+template <int SIGN> struct Dft<6, SIGN> : DftComp<2, 3, SIGN> {};
+template <int SIGN> struct Dft<9, SIGN> : DftComp<3, 3, SIGN> {};
+template <int SIGN> struct Dft<12, SIGN> : DftComp<4, 3, SIGN> {};
+template <int SIGN> struct Dft<16, SIGN> : DftComp<4, 4, SIGN> {};
+template <int SIGN> struct Dft<18, SIGN> : DftComp<2, 9, SIGN> {};
+template <int SIGN> struct Dft<24, SIGN> : DftComp<8, 3, SIGN> {};
+template <int SIGN> struct Dft<27, SIGN> : DftComp<3, 9, SIGN> {};
+template <int SIGN> struct Dft<32, SIGN> : DftComp<8, 4, SIGN> {};
 
 // ------------------------------------------------------ stage schedule ---
 struct Radices {
@@ -143,23 +219,50 @@ struct Radices {
     int r[24];
 };
 
-// Radix schedule for a length N = 2^a 3^b: radix-3 stages first, then the
-// power of two in radix-8 stages, with one radix-16, radix-4 or radix-2 stage
-// to take up the remainder.
-constexpr Radices make_radices(int N) {
+constexpr bool has_dft(int r, int rmax) {
+    return r <= rmax && (r == 2 || r == 3 || r == 4 || r == 6 || r == 8 || r == 9 || r == 12 || r == 16 ||
+                         r == 18 || r == 24 || r == 27 || r == 32);
+}
+
+// Smallest possible largest factor when N splits into exactly `s` radices,
+// each at most rmax with a DFT above (0: impossible).
+constexpr int best_max(int N, int s, int rmax) {
+    if (s == 1) return has_dft(N, rmax) ? N : 0;
+    int best = 0;
+    for (int r = 2; r <= rmax; ++r) {
+        if (N % r || !has_dft(r, rmax)) continue;
+        const int m = best_max(N / r, s - 1, rmax);
+        if (!m) continue;
+        const int worst = m > r ? m : r;
+        if (!best || worst < best) best = worst;
+    }
+    return best;
+}
+
+// Radix schedules: plan 0 allows radices up to 32 (fewest stages, most
+// registers), plan 1 up to 16, plan 2 up to 8.
+constexpr int plan_rmax(int plan) { return plan == 0 ? 32 : (plan == 1 ? 16 : 8); }
+
+// Stage radices of a length N = 2^a 3^b: the fewest stages allowed by the
+// plan's largest radix, then the most even split; ascending order.
+constexpr Radices make_radices(int N, int plan = 0) {
     Radices R{0, {}};
+    if (N <= 1) return R;
+    const int rmax = plan_rmax(plan);   // every 2^a 3^b splits into radices 2 and 3
+    int s = 1;
+    while (!best_max(N, s, rmax)) ++s;
     int m = N;
-    while (m % 3 == 0) { R.r[R.n++] = 3; m /= 3; }
-    int e = 0;
-    while (m % 2 == 0) { ++e; m /= 2; }
-    int first = 0;
-    if (e % 3 == 1) first = (e >= 4) ? 16 : 2;
-    else if (e % 3 == 2) first = 4;
-    if (first == 16) e -= 4;
-    else if (first == 4) e -= 2;
-    else if (first == 2) e -= 1;
-    if (first) R.r[R.n++] = first;
-    while (e >= 3) { R.r[R.n++] = 8; e -= 3; }
+    for (int left = s; left > 1; --left) {
+        const int cap = best_max(m, left, rmax);
+        int pick = 0;   // smallest radix that keeps the remaining split within cap
+        for (int r = 2; r <= cap && !pick; ++r)
+            if (m % r == 0 && has_dft(r, rmax) && best_max(m / r, left - 1, rmax) &&
+                best_max(m / r, left - 1, rmax) <= cap)
+                pick = r;
+        R.r[R.n++] = pick;
+        m /= pick;
+    }
+    R.r[R.n++] = m;
     return R;
 }
 
@@ -176,68 +279,80 @@ constexpr int stage_ns(const Radices& R, int s) {
 }
 
 // --------------------------------------------------------- storage types ---
+// All pass data lives in device (global) memory; the explicit address space
+// keeps accesses as global loads/stores even in code that is not inlined into
+// a kernel, where pointers would otherwise be generic (flat).
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <class T> using gptr = __attribute__((address_space(1))) T*;
+template <class T> using gcptr = const __attribute__((address_space(1))) T*;
+template <class T> __device__ __forceinline__ gcptr<T> gload_ptr(const void* p) { return (gcptr<T>)p; }
+template <class T> __device__ __forceinline__ gptr<T> gstore_ptr(void* p) { return (gptr<T>)p; }
+
 
 struct IoC64 {   // complex64: FP32 re, FP32 im
     static constexpr int bytes = 8;
     static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
-        return reinterpret_cast<const float2*>(p)[i];
+        const f32x2 v = gload_ptr<f32x2>(p)[i];
+        return make_float2(v.x, v.y);
     }
     static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
-        reinterpret_cast<float2*>(p)[i] = v;
+        f32x2 w;
+        w.x = v.x;
+        w.y = v.y;
+        gstore_ptr<f32x2>(p)[i] = w;
     }
     // streaming variants: data touched once per pass, no reuse in cache
     static __device__ __forceinline__ float2 load_nt(const void* p, int64_t i) {
-        const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p) + i);
+        const f32x2 v = __builtin_nontemporal_load(gload_ptr<f32x2>(p) + i);
         return make_float2(v.x, v.y);
     }
     // elements i and i+1 in one access (i even, 16-byte aligned)
     static __device__ __forceinline__ void load2_nt(const void* p, int64_t i, float2& a, float2& b) {
-        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + i / 2);
+        const f32x4 v = __builtin_nontemporal_load(gload_ptr<f32x4>(p) + i / 2);
         a = make_float2(v.x, v.y);
         b = make_float2(v.z, v.w);
     }
     static __device__ __forceinline__ void store2_nt(void* p, int64_t i, float2 a, float2 b) {
         f32x4 w;
         w.x = a.x; w.y = a.y; w.z = b.x; w.w = b.y;
-        __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p) + i / 2);
+        __builtin_nontemporal_store(w, gstore_ptr<f32x4>(p) + i / 2);
     }
     static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
         f32x2 w;
         w.x = v.x;
         w.y = v.y;
-        __builtin_nontemporal_store(w, reinterpret_cast<f32x2*>(p) + i);
+        __builtin_nontemporal_store(w, gstore_ptr<f32x2>(p) + i);
     }
 };
 
 struct IoF16 {   // FP16 re, FP16 im
     static constexpr int bytes = 4;
     static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
-        const __half2 h = reinterpret_cast<const __half2*>(p)[i];
-        return __half22float2(h);
+        const uint32_t w = gload_ptr<uint32_t>(p)[i];
+        return __half22float2(__builtin_bit_cast(__half2, w));
     }
     static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
-        reinterpret_cast<__half2*>(p)[i] = __float22half2_rn(v);
+        gstore_ptr<uint32_t>(p)[i] = __builtin_bit_cast(uint32_t, __float22half2_rn(v));
     }
     static __device__ __forceinline__ float2 load_nt(const void* p, int64_t i) {
-        const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p) + i);
+        const uint32_t w = __builtin_nontemporal_load(gload_ptr<uint32_t>(p) + i);
         return __half22float2(__builtin_bit_cast(__half2, w));
     }
     static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
         __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, __float22half2_rn(v)),
-                                    reinterpret_cast<uint32_t*>(p) + i);
+                                    gstore_ptr<uint32_t>(p) + i);
     }
     // pairs move as one 64-bit scalar access
     static __device__ __forceinline__ void load2_nt(const void* p, int64_t i, float2& a, float2& b) {
-        const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(p) + i / 2);
+        const uint64_t w = __builtin_nontemporal_load(gload_ptr<uint64_t>(p) + i / 2);
         a = __half22float2(__builtin_bit_cast(__half2, (uint32_t)w));
         b = __half22float2(__builtin_bit_cast(__half2, (uint32_t)(w >> 32)));
     }
     static __device__ __forceinline__ void store2_nt(void* p, int64_t i, float2 a, float2 b) {
         const uint64_t w = (uint64_t)__builtin_bit_cast(uint32_t, __float22half2_rn(a)) |
                            ((uint64_t)__builtin_bit_cast(uint32_t, __float22half2_rn(b)) << 32);
-        __builtin_nontemporal_store(w, reinterpret_cast<uint64_t*>(p) + i / 2);
+        __builtin_nontemporal_store(w, gstore_ptr<uint64_t>(p) + i / 2);
     }
 };
 
@@ -251,22 +366,22 @@ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
 struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
     static constexpr int bytes = 4;
     static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
-        const uint32_t w = reinterpret_cast<const uint32_t*>(p)[i];
+        const uint32_t w = gload_ptr<uint32_t>(p)[i];
         return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
     }
     static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
-        reinterpret_cast<uint32_t*>(p)[i] = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
+        gstore_ptr<uint32_t>(p)[i] = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
     }
     static __device__ __forceinline__ float2 load_nt(const void* p, int64_t i) {
-        const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p) + i);
+        const uint32_t w = __builtin_nontemporal_load(gload_ptr<uint32_t>(p) + i);
         return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
     }
     static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
         __builtin_nontemporal_store(f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16),
-                                    reinterpret_cast<uint32_t*>(p) + i);
+                                    gstore_ptr<uint32_t>(p) + i);
     }
     static __device__ __forceinline__ void load2_nt(const void* p, int64_t i, float2& a, float2& b) {
-        const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(p) + i / 2);
+        const uint64_t w = __builtin_nontemporal_load(gload_ptr<uint64_t>(p) + i / 2);
         const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
         a = make_float2(__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u));
         b = make_float2(__uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u));
@@ -274,7 +389,7 @@ struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
     static __device__ __forceinline__ void store2_nt(void* p, int64_t i, float2 a, float2 b) {
         const uint64_t w = (uint64_t)(f32_to_bf16_rne(a.x) | (f32_to_bf16_rne(a.y) << 16)) |
                            ((uint64_t)(f32_to_bf16_rne(b.x) | (f32_to_bf16_rne(b.y) << 16)) << 32);
-        __builtin_nontemporal_store(w, reinterpret_cast<uint64_t*>(p) + i / 2);
+        __builtin_nontemporal_store(w, gstore_ptr<uint64_t>(p) + i / 2);
     }
 };
 
@@ -348,7 +463,7 @@ struct BatchTable {
 // or columns (strided layout) per workgroup.  K: the strided layout's LDS
 // exchanges run in K rounds over N/K rows each, so a wide tile needs only
 // 1/K of its size in LDS and more workgroups stay resident per CU.
-template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1>
+template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1, int PLAN = 0>
 struct PencilPass {
     static_assert(STRIDED || K == 1, "split exchanges are for the strided layout");
     static_assert(N % K == 0, "K must divide N");
@@ -363,7 +478,7 @@ struct PencilPass {
         if constexpr (NT) IO::store_nt(p, i, v);
         else IO::store(p, i, v);
     }
-    static constexpr Radices RD = make_radices(N);
+    static constexpr Radices RD = make_radices(N, PLAN);
     static constexpr int NS = RD.n;
     static constexpr int ROWS = N / K;   // LDS rows per exchange round
     // LDS layout: strided tiles store [element][column] with one float2 of
@@ -371,7 +486,14 @@ struct PencilPass {
     // float2 of padding after every 2^PADSH elements, which spreads the
     // radix-stride writes of the first stages over all banks.
     static constexpr bool PAIRS = !STRIDED && (FLAGS & kFlagPairs) != 0;
-    static constexpr int PADSH = PAIRS ? 4 : 3;
+    // first-stage writes land R0 (times the slots per thread, when paired)
+    // elements apart: pad once per that many elements
+    static constexpr int pad_shift() {
+        int r = RD.r[0] * (PAIRS ? ((N / RD.r[0] + T - 1) / T) : 1), sh = 0;
+        while (r % 2 == 0) { r /= 2; ++sh; }
+        return sh < 3 ? 3 : (sh > 6 ? 6 : sh);
+    }
+    static constexpr int PADSH = pad_shift();
     static constexpr int LDS_ROW = STRIDED ? (P + 1) : (N + (N >> PADSH) + 1);
     static constexpr int LDS_ELEMS = STRIDED ? ROWS * (P + 1) : P * LDS_ROW;
     static constexpr int lds_bytes() { return (LDS_ELEMS + (PERSIST ? N : 0)) * 8; }
@@ -447,6 +569,15 @@ struct PencilPass {
         int64_t base_in, base_out;
     };
 
+    // Twiddle table entry: in LDS for persistent kernels, else in global memory.
+    __device__ __forceinline__ static float2 tw_at(const float2* tw, int i) {
+        if constexpr (PERSIST) return tw[i];
+        else {
+            const f32x2 w = gload_ptr<f32x2>(tw)[i];
+            return make_float2(w.x, w.y);
+        }
+    }
+
     template <int S>
     __device__ __forceinline__ static void butterflies(float2* v, int j, const float2* tw) {
         using Q = St<S>;
@@ -459,7 +590,7 @@ struct PencilPass {
                 const int k = b % Q::Ns;
 #pragma unroll
                 for (int r = 1; r < Q::R; ++r) {
-                    float2 w = tw[k * r * Q::TWS];
+                    float2 w = tw_at(tw, k * r * Q::TWS);
                     if (SIGN > 0) w.y = -w.y;
                     u[r] = cmul(u[r], w);
                 }
@@ -512,7 +643,8 @@ struct PencilPass {
     // e < N, so g*e < M: no reduction needed.
     __device__ __forceinline__ static float2 tw4_of(int e, int64_t col, int64_t o1, const PassArgs& a) {
         const int64_t g = a.tw4_mode == 1 ? col : o1;
-        float2 w = a.tw4[g * e];
+        const f32x2 wv = gload_ptr<f32x2>(a.tw4)[g * e];
+        float2 w = make_float2(wv.x, wv.y);
         if (SIGN > 0) w.y = -w.y;
         return w;
     }
@@ -700,6 +832,14 @@ struct PencilPass {
         }
     }
 
+    // One tile; the caller owns the LDS and synchronises before reusing it.
+    __device__ __forceinline__ static void run_tile(const PassArgs& a, int64_t t, float2* lds) {
+        const Ctx c = make_ctx(a, t);
+        float2 v[maxv()];
+        load_first(v, c, a);
+        stages<0>(lds, v, c, a, a.tw);
+    }
+
     __device__ __forceinline__ static void run(const PassArgs& a0, const BatchTable& bt, float2* lds) {
         if constexpr (!PERSIST) {
             // A merged batch launch first picks its array; both kinds of
@@ -754,10 +894,10 @@ struct PencilPass {
     }
 };
 
-template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1>
+template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1, int PLAN = 0>
 __global__ __launch_bounds__(T * P) void pencil_pass_kernel(PassArgs a, BatchTable bt) {
     extern __shared__ float2 lds_dyn[];
-    PencilPass<N, T, P, STRIDED, IO, SIGN, FLAGS, K>::run(a, bt, lds_dyn);
+    PencilPass<N, T, P, STRIDED, IO, SIGN, FLAGS, K, PLAN>::run(a, bt, lds_dyn);
 }
 
 }  // namespace wsfft

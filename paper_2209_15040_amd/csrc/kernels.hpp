@@ -11,19 +11,23 @@ struct PassKernel {
     int n;              // pencil length
     bool strided;       // layout: columns unit-stride (true) or pencils contiguous
     bool four_step;     // compiled with the split-axis first-pass features
+    int variant;        // 0: default; 1: radix <= 8 plan; 2: half-width strided tiles
     int threads;        // workgroup size
     int per_block;      // pencils (contiguous) or columns (strided) per workgroup
     int lds_bytes;      // dynamic LDS per workgroup
+    int plan;           // radix plan (make_radices)
     // bt == nullptr: one array described by the PassArgs; otherwise a merged
     // batch of direct passes (PassArgs supplies the shared fields)
     hipError_t (*launch)(const PassArgs&, const BatchTable* bt, dim3 grid, hipStream_t);
     hipError_t (*prepare)();   // one-time function attributes
 };
 
-// NULL when no kernel of that length/layout exists.
-const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided, bool four_step);
+// NULL when no kernel of that length/layout/variant exists.
+const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided, bool four_step,
+                                   int variant = 0);
+constexpr int kMaxVariants = 3;
 
-#define WSFFT_DECLARE_FIND(NAME) const PassKernel* NAME(int n, bool strided, bool four_step);
+#define WSFFT_DECLARE_FIND(NAME) const PassKernel* NAME(int n, bool strided, bool four_step, int variant);
 WSFFT_DECLARE_FIND(find_pass_c64_neg)
 WSFFT_DECLARE_FIND(find_pass_c64_pos)
 WSFFT_DECLARE_FIND(find_pass_f16_neg)

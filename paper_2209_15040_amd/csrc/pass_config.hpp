@@ -22,16 +22,16 @@ constexpr int kLdsBytesMax = 160 * 1024;   // LDS per CU on gfx950
 constexpr int kLdsRoundBudget = 36 * 1024; // target LDS per strided workgroup
 constexpr int kPassFlags = kFlagNontemporal;
 
-constexpr int cfg_T_contig(int N) {
+constexpr int cfg_T_contig(int N, int plan = 0) {
     int t = N / 16;
     if (t < 1) t = 1;
     // every thread must own at least one butterfly of the widest stage
-    const int tmax = N / max_radix(make_radices(N));
+    const int tmax = N / max_radix(make_radices(N, plan));
     if (tmax >= 1 && t > tmax) t = tmax;
     return t > 1024 ? 1024 : t;
 }
-constexpr int cfg_P_contig(int N) {
-    const int p = 256 / cfg_T_contig(N);
+constexpr int cfg_P_contig(int N, int plan = 0) {
+    const int p = 256 / cfg_T_contig(N, plan);
     return p < 1 ? 1 : p;
 }
 
@@ -44,24 +44,24 @@ constexpr int pow2_floor(int n) {
 
 // Elements per thread in the strided layout: 32 for powers of two; radix-3
 // stages leave some threads idle, so fewer there to stay within registers.
-constexpr int cfg_T_strided(int N, int bytes) {
+constexpr int cfg_T_strided(int N, int bytes, int plan = 0) {
     (void)bytes;
     const int e = is_pow2(N) ? 32 : 24;
     int t = (N + e - 1) / e;
-    const int tmax = N / max_radix(make_radices(N));
+    const int tmax = N / max_radix(make_radices(N, plan));
     if (tmax >= 1 && t > tmax) t = tmax;
     return t < 1 ? 1 : t;
 }
-constexpr int cfg_P_strided(int N, int bytes) {
+constexpr int cfg_P_strided(int N, int bytes, int plan = 0) {
     int p = bytes == 8 ? 32 : 64;
     if (N <= 64) p = 64;                   // one full wave of columns at least
-    const int cap = pow2_floor(1024 / cfg_T_strided(N, bytes));
+    const int cap = pow2_floor(1024 / cfg_T_strided(N, bytes, plan));
     return p > cap ? cap : p;
 }
 // Smallest K dividing N whose exchange round fits the LDS budget; when that
 // takes more than 8 rounds, accept up to twice the budget instead.
-constexpr int cfg_K_strided(int N, int bytes) {
-    const int p = cfg_P_strided(N, bytes);
+constexpr int cfg_K_strided(int N, int bytes, int plan = 0) {
+    const int p = cfg_P_strided(N, bytes, plan);
     int first = 0;
     for (int k = 1; k <= N && !first; ++k)
         if (N % k == 0 && (N / k) * (p + 1) * 8 <= kLdsRoundBudget) first = k;

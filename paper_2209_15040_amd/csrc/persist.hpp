@@ -1,0 +1,35 @@
+// Persistent batched launch (persist.hip): shared host/device types.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "fft_device.hpp"
+
+namespace wsfft {
+
+constexpr int kPersistThreads = 256;
+
+// One superstep of one array.
+struct PersistPass {
+    PassArgs a;          // resolved arguments (buffers, geometry, scale)
+    int64_t first;       // index of its first tile in the launch's work list
+    int64_t tiles;
+    int32_t type;        // kernel branch (persist_type)
+    int32_t dep;         // pass that must be complete first, or -1
+};
+
+// Device-resident counters owned by one batch plan.
+struct PersistCounters {
+    unsigned ticket;     // next work item
+    unsigned finished;   // workgroups that left
+    unsigned error;      // nonzero: a dependency wait timed out
+    unsigned pad;
+    unsigned done[1];    // tiles published per pass (npasses entries)
+};
+
+int persist_type(int n, bool strided);        // -1: no persistent kernel for it
+int persist_per_block(int n, bool strided);   // pencils or columns per workgroup
+int persist_lds_bytes();
+hipError_t persist_prepare(int* blocks_per_cu);
+hipError_t persist_launch(int sign, const PersistPass* passes, int npasses, int64_t total, PersistCounters* ctr,
+                          unsigned grid, unsigned spin_limit, hipStream_t s);
+
+}  // namespace wsfft

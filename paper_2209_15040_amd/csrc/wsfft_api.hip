@@ -15,11 +15,17 @@
 // Pass A cannot run in place, so split axes go first and read the input.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -27,6 +33,7 @@
 #include "../../include/wsfft.h"
 #include "kernels.hpp"
 #include "pass_config.hpp"
+#include "persist.hpp"
 
 using namespace wsfft;
 
@@ -50,6 +57,7 @@ struct Pass {
     int64_t tw_off, tw4_off;      // element offsets into the twiddle block (tw4: -1 none)
     float pass_scale;             // 2^-s_p
     int outer_dim;                // count whose stride spans whole arrays: 0 = C, 1 = O1, 2 = O2
+    int variant;                  // kernel launch variant (autotuner)
     dim3 grid;
 };
 
@@ -234,6 +242,189 @@ const char* kind_name(wsfft_dtype_t d) {
     return d == WSFFT_C64 ? "c64" : (d == WSFFT_C16_FP16 ? "c16-fp16" : "c16-bf16");
 }
 
+void describe_plan(wsfft_plan_s* plan) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%lldx%lldx%lld %s sign=%d S=%d:", (long long)plan->n[0], (long long)plan->n[1],
+                  (long long)plan->n[2], kind_name(plan->dtype), plan->sign, plan->scale_log2);
+    plan->desc = buf;
+    for (const Pass& P : plan->passes) {
+        std::snprintf(buf, sizeof buf, " %c%s[%s n=%lld v%d wg=%d per=%d lds=%d grid=%u]", "xyz"[P.axis],
+                      P.four_step == 1 ? "A" : (P.four_step == 2 ? "B" : ""), P.strided ? "strided" : "contig",
+                      (long long)P.n, P.variant, P.kern_neg->threads, P.kern_neg->per_block, P.kern_neg->lds_bytes,
+                      P.grid.x);
+        plan->desc += buf;
+    }
+}
+
+// ---- autotuner -------------------------------------------------------------------
+// Each pass of a hot length has several compiled launch variants (radix plan,
+// tile width).  The choice per pass geometry is read from a cache file, and,
+// when tuning is requested (WSFFT_FLAG_TUNE or WSFFT_TUNE=1), measured at plan
+// creation with HIP events on scratch buffers and appended to the cache.
+// WSFFT_TUNE=0 disables both.  Cache: $WSFFT_TUNE_CACHE, else
+// $HOME/.cache/wsfft_tune.txt, one "key variant microseconds" line per entry.
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+bool g_tune_loaded = false;
+
+std::string tune_cache_path() {
+    const char* e = std::getenv("WSFFT_TUNE_CACHE");
+    if (e && *e) return e;
+    const char* h = std::getenv("HOME");
+    return std::string(h && *h ? h : "/tmp") + "/.cache/wsfft_tune.txt";
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    std::ifstream f(tune_cache_path());
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream ls(line);
+        std::string key;
+        int v = -1;
+        if (ls >> key >> v && v >= 0 && v < kMaxVariants) g_tune_cache[key] = v;
+    }
+}
+
+void tune_store_locked(const std::string& key, int v, double us) {
+    g_tune_cache[key] = v;
+    const std::string path = tune_cache_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << " " << v << " " << us << "\n";
+}
+
+std::string tune_key(const wsfft_plan_s* plan, const Pass& P, const char* arch) {
+    const PassArgs& a = P.args;
+    char buf[320];
+    std::snprintf(buf, sizeof buf, "%s|%s|s%d|n%lld|st%d|fs%d|C%lld|O%lld,%lld|es%lld|os%lld,%lld", arch,
+                  kind_name(plan->dtype), plan->sign, (long long)P.n, (int)P.strided, P.four_step,
+                  (long long)a.C, (long long)a.O1, (long long)a.O2, (long long)a.es_in, (long long)a.os1_in,
+                  (long long)a.os2_in);
+    return buf;
+}
+
+bool use_variant(wsfft_plan_s* plan, Pass& P, int v) {
+    const StorageKind kind = kind_of(plan->dtype);
+    const PassKernel* kn = find_pass_kernel(kind, -1, (int)P.n, P.strided, P.four_step == 1, v);
+    const PassKernel* kp = find_pass_kernel(kind, +1, (int)P.n, P.strided, P.four_step == 1, v);
+    if (!kn || !kp || kn->prepare() != hipSuccess || kp->prepare() != hipSuccess) return false;
+    const int64_t blocks = blocks_for(P, kn);
+    if (blocks < 1 || blocks * kn->threads > 0xffffffffLL) return false;
+    P.kern_neg = kn;
+    P.kern_pos = kp;
+    P.variant = v;
+    P.grid = dim3((unsigned)blocks);
+    return true;
+}
+
+// Median-free best-of timing: microseconds per launch of pass P with variant v.
+double time_variant(wsfft_plan_s* plan, Pass& P, int v, void* buf0, void* buf1, hipStream_t st) {
+    Pass Q = P;
+    if (!use_variant(plan, Q, v)) return -1.0;
+    const PassKernel* k = plan->sign < 0 ? Q.kern_neg : Q.kern_pos;
+    PassArgs a = Q.args;
+    a.src = Q.src_sel == 0 ? buf0 : buf1;
+    a.dst = Q.dst_sel == 0 ? buf0 : buf1;
+    a.scale = Q.pass_scale;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0;
+    }
+    double best = -1.0;
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i) ok = k->launch(a, nullptr, Q.grid, st) == hipSuccess;
+    for (int rep = 0; rep < 3 && ok; ++rep) {
+        ok = hipEventRecord(e0, st) == hipSuccess;
+        for (int i = 0; i < 3 && ok; ++i) ok = k->launch(a, nullptr, Q.grid, st) == hipSuccess;
+        ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+            const double us = 1000.0 * ms / 3;
+            if (best < 0 || us < best) best = us;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ok ? best : -1.0;
+}
+
+void tune_plan(wsfft_plan_s* plan, bool requested) {
+    const char* force = std::getenv("WSFFT_TUNE_FORCE");   // diagnostic: one variant everywhere
+    if (force && *force) {
+        const int v = std::atoi(force);
+        for (Pass& P : plan->passes) {
+            Pass Q = P;
+            if (v >= 0 && v < kMaxVariants && use_variant(plan, Q, v)) P = Q;
+        }
+        (void)hipGetLastError();
+        return;
+    }
+    const char* env = std::getenv("WSFFT_TUNE");
+    if (env && std::strcmp(env, "0") == 0) return;
+    requested = requested || (env && std::strcmp(env, "1") == 0);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, plan->device) != hipSuccess) return;
+    const char* arch = prop.gcnArchName;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load_locked();
+    void* buf0 = nullptr;
+    void* buf1 = nullptr;
+    hipStream_t st = nullptr;
+    const int64_t bytes = plan->n[0] * plan->n[1] * plan->n[2] * elem_bytes(plan->dtype);
+    for (Pass& P : plan->passes) {
+        const StorageKind kind = kind_of(plan->dtype);
+        int nvar = 0;
+        for (int v = 0; v < kMaxVariants; ++v)
+            if (find_pass_kernel(kind, plan->sign, (int)P.n, P.strided, P.four_step == 1, v)) ++nvar;
+        if (nvar < 2) continue;
+        const std::string key = tune_key(plan, P, arch);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            Pass Q = P;
+            if (use_variant(plan, Q, it->second)) P = Q;
+            continue;
+        }
+        if (!requested) continue;
+        if (!buf0) {
+            if (hipMalloc(&buf0, (size_t)bytes) != hipSuccess) { buf0 = nullptr; break; }
+            if (hipMalloc(&buf1, (size_t)bytes) != hipSuccess) { buf1 = nullptr; break; }
+            if (hipMemset(buf0, 0, (size_t)bytes) != hipSuccess || hipMemset(buf1, 0, (size_t)bytes) != hipSuccess ||
+                hipStreamCreate(&st) != hipSuccess) {
+                st = nullptr;
+                break;
+            }
+        }
+        int best_v = -1;
+        double best_us = 0.0;
+        for (int v = 0; v < kMaxVariants; ++v) {
+            if (!find_pass_kernel(kind, plan->sign, (int)P.n, P.strided, P.four_step == 1, v)) continue;
+            const double us = time_variant(plan, P, v, buf0, buf1, st);
+            if (us > 0 && (best_v < 0 || us < best_us)) {
+                best_v = v;
+                best_us = us;
+            }
+        }
+        if (best_v >= 0) {
+            Pass Q = P;
+            if (use_variant(plan, Q, best_v)) {
+                P = Q;
+                tune_store_locked(key, best_v, best_us);
+            }
+        }
+    }
+    if (st) (void)hipStreamDestroy(st);
+    if (buf0) (void)hipFree(buf0);
+    if (buf1) (void)hipFree(buf1);
+    (void)hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
@@ -263,7 +454,7 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     if (sign != 1 && sign != -1) return fail(WSFFT_ERROR_INVALID_VALUE);
     if (dtype != WSFFT_C64 && dtype != WSFFT_C16_FP16 && dtype != WSFFT_C16_BF16)
         return fail(WSFFT_ERROR_INVALID_VALUE);
-    if (flags & ~WSFFT_FLAG_FP32_TWIDDLES) return fail(WSFFT_ERROR_INVALID_VALUE);
+    if (flags & ~(WSFFT_FLAG_FP32_TWIDDLES | WSFFT_FLAG_TUNE)) return fail(WSFFT_ERROR_INVALID_VALUE);
     const int64_t dims[3] = {nx, ny, nz};
     for (int64_t d : dims)
         if (d > WSFFT_MAX_AXIS || !is_smooth23(d)) return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
@@ -372,19 +563,6 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     const int64_t N = nx * ny * nz;
     if (nsplit > 1) plan->work_bytes = N * elem_bytes(dtype);
 
-    // description
-    char buf[256];
-    std::snprintf(buf, sizeof buf, "%lldx%lldx%lld %s sign=%d S=%d:", (long long)nx, (long long)ny,
-                  (long long)nz, kind_name(dtype), sign, S);
-    plan->desc = buf;
-    for (const Pass& P : plan->passes) {
-        std::snprintf(buf, sizeof buf, " %c%s[%s n=%lld wg=%d per=%d lds=%d grid=%u]", "xyz"[P.axis],
-                      P.four_step == 1 ? "A" : (P.four_step == 2 ? "B" : ""),
-                      P.strided ? "strided" : "contig", (long long)P.n, P.kern_neg->threads,
-                      P.kern_neg->per_block, P.kern_neg->lds_bytes, P.grid.x);
-        plan->desc += buf;
-    }
-
     // ---- device ------------------------------------------------------------
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { delete plan; return fail(WSFFT_ERROR_NO_DEVICE); }
@@ -427,6 +605,8 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
             return fail(WSFFT_ERROR_HIP);
         }
     }
+    tune_plan(plan, (flags & WSFFT_FLAG_TUNE) != 0);
+    describe_plan(plan);
     {
         std::lock_guard<std::mutex> g(g_plans_mu);
         g_plans.insert(plan);
@@ -678,14 +858,175 @@ wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const
 
 namespace wsfft {
 
-const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided, bool four_step) {
+const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided, bool four_step, int v) {
     switch (kind) {
-        case kC64: return sign < 0 ? find_pass_c64_neg(n, strided, four_step) : find_pass_c64_pos(n, strided, four_step);
-        case kF16: return sign < 0 ? find_pass_f16_neg(n, strided, four_step) : find_pass_f16_pos(n, strided, four_step);
+        case kC64:
+            return sign < 0 ? find_pass_c64_neg(n, strided, four_step, v) : find_pass_c64_pos(n, strided, four_step, v);
+        case kF16:
+            return sign < 0 ? find_pass_f16_neg(n, strided, four_step, v) : find_pass_f16_pos(n, strided, four_step, v);
         case kBF16:
-            return sign < 0 ? find_pass_bf16_neg(n, strided, four_step) : find_pass_bf16_pos(n, strided, four_step);
+            return sign < 0 ? find_pass_bf16_neg(n, strided, four_step, v) : find_pass_bf16_pos(n, strided, four_step, v);
     }
     return nullptr;
 }
 
 }  // namespace wsfft
+
+// ---- batch plans: one persistent launch per execution -----------------------------
+
+struct wsfft_batch_plan_s {
+    int device;
+    int sign;                  // effective kernel sign of every pass
+    int npasses;
+    int64_t total;             // work items (tiles) of one execution
+    unsigned grid;
+    wsfft::PersistPass* d_passes = nullptr;
+    wsfft::PersistCounters* d_ctr = nullptr;
+};
+
+namespace {
+std::mutex g_batch_mu;
+std::unordered_set<const wsfft_batch_plan_s*> g_batches;
+thread_local wsfft_status_t g_batch_error = WSFFT_SUCCESS;
+
+wsfft_batch_plan_t batch_fail(wsfft_status_t st) {
+    g_batch_error = st;
+    return nullptr;
+}
+bool batch_live(const wsfft_batch_plan_s* b) {
+    if (!b) return false;
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    return g_batches.count(b) != 0;
+}
+}  // namespace
+
+extern "C" {
+
+wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans, const void* const* in,
+                                           void* const* out, int adjoint) {
+    using namespace wsfft;
+    if (count < 1) return batch_fail(WSFFT_ERROR_INVALID_VALUE);
+    if (!plans || !in || !out) return batch_fail(WSFFT_ERROR_NULL_POINTER);
+    int sign = 0;
+    size_t maxp = 0;
+    for (int i = 0; i < count; ++i) {
+        const wsfft_status_t st = check_exec(plans[i], in[i], out[i]);
+        if (st != WSFFT_SUCCESS) return batch_fail(st);
+        const wsfft_plan_s* p = plans[i];
+        if (p->dtype != WSFFT_C64 || p->work_bytes > 0) return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+        const int s = adjoint ? -p->sign : p->sign;
+        if (sign == 0) sign = s;
+        if (s != sign) return batch_fail(WSFFT_ERROR_INVALID_VALUE);
+        for (const Pass& P : p->passes)
+            if (P.four_step != 0 || persist_type((int)P.n, P.strided) < 0)
+                return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+        maxp = std::max(maxp, p->passes.size());
+    }
+    // superstep-major list of passes; dep = same array, previous superstep
+    std::vector<PersistPass> list;
+    std::vector<int> last(count, -1);
+    int64_t total = 0;
+    for (size_t pi = 0; pi < maxp; ++pi)
+        for (int i = 0; i < count; ++i) {
+            const wsfft_plan_s* p = plans[i];
+            if (pi >= p->passes.size()) continue;
+            const Pass& P = p->passes[pi];
+            PersistPass q{};
+            q.a = P.args;
+            const bool ip = in[i] == out[i];
+            const int ss = ip ? P.src_sel_ip : P.src_sel, ds = ip ? P.dst_sel_ip : P.dst_sel;
+            q.a.src = ss == 0 ? in[i] : out[i];
+            q.a.dst = ds == 0 ? const_cast<void*>(in[i]) : out[i];
+            q.a.scale = P.pass_scale;
+            const int64_t per = persist_per_block((int)P.n, P.strided);
+            q.tiles = P.strided ? ((q.a.C + per - 1) / per) * q.a.O1 * q.a.O2 : (q.a.C + per - 1) / per;
+            q.type = persist_type((int)P.n, P.strided);
+            q.dep = last[i];
+            q.first = total;
+            total += q.tiles;
+            last[i] = (int)list.size();
+            list.push_back(q);
+        }
+    // tickets are 32-bit and every workgroup draws one past the end
+    if (list.empty() || total > 0x7fffffffLL) return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+    wsfft_batch_plan_s* b = new (std::nothrow) wsfft_batch_plan_s();
+    if (!b) return batch_fail(WSFFT_ERROR_OUT_OF_MEMORY);
+    b->device = plans[0]->device;
+    b->sign = sign;
+    b->npasses = (int)list.size();
+    b->total = total;
+    int per_cu = 0, cus = 0;
+    if (persist_prepare(&per_cu) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
+        delete b;
+        return batch_fail(WSFFT_ERROR_HIP);
+    }
+    b->grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(total, (int64_t)std::max(1, per_cu) * cus));
+    const size_t ctr_bytes = sizeof(PersistCounters) + sizeof(unsigned) * (size_t)list.size();
+    if (hipMalloc(&b->d_passes, sizeof(PersistPass) * list.size()) != hipSuccess) {
+        delete b;
+        return batch_fail(WSFFT_ERROR_OUT_OF_MEMORY);
+    }
+    if (hipMalloc(&b->d_ctr, ctr_bytes) != hipSuccess) {
+        (void)hipFree(b->d_passes);
+        delete b;
+        return batch_fail(WSFFT_ERROR_OUT_OF_MEMORY);
+    }
+    if (hipMemcpy(b->d_passes, list.data(), sizeof(PersistPass) * list.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(b->d_ctr, 0, ctr_bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(b->d_passes);
+        (void)hipFree(b->d_ctr);
+        delete b;
+        return batch_fail(WSFFT_ERROR_HIP);
+    }
+    {
+        std::lock_guard<std::mutex> g(g_batch_mu);
+        g_batches.insert(b);
+    }
+    g_batch_error = WSFFT_SUCCESS;
+    return b;
+}
+
+wsfft_status_t wsfft_batch_get_last_error(void) { return g_batch_error; }
+
+wsfft_status_t wsfft_batch_execute(wsfft_batch_plan_t b, hipStream_t stream) {
+    if (!batch_live(b)) return WSFFT_ERROR_INVALID_PLAN;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
+    if (cur != b->device) return WSFFT_ERROR_WRONG_DEVICE;
+    // a dependency wait gives up after 2^22 polls (well under a second per
+    // wait, far beyond any tile's duration): a bug cannot hang the GPU
+    return wsfft::persist_launch(b->sign, b->d_passes, b->npasses, b->total, b->d_ctr, b->grid, 1u << 22, stream) ==
+                   hipSuccess
+               ? WSFFT_SUCCESS
+               : WSFFT_ERROR_HIP;
+}
+
+int64_t wsfft_batch_plan_tiles(wsfft_batch_plan_t b) { return batch_live(b) ? b->total : -1; }
+
+wsfft_status_t wsfft_batch_plan_check(wsfft_batch_plan_t b, int* timed_out) {
+    if (!batch_live(b)) return WSFFT_ERROR_INVALID_PLAN;
+    if (!timed_out) return WSFFT_ERROR_NULL_POINTER;
+    unsigned err = 0;
+    if (hipMemcpy(&err, &b->d_ctr->error, sizeof err, hipMemcpyDeviceToHost) != hipSuccess) return WSFFT_ERROR_HIP;
+    *timed_out = err != 0;
+    return WSFFT_SUCCESS;
+}
+
+void wsfft_batch_plan_destroy(wsfft_batch_plan_t b) {
+    if (!b) return;
+    {
+        std::lock_guard<std::mutex> g(g_batch_mu);
+        if (!g_batches.erase(b)) return;
+    }
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b->d_passes);
+    (void)hipFree(b->d_ctr);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    delete b;
+}
+
+}  // extern "C"

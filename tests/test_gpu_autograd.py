@@ -39,8 +39,9 @@ def test_ifftn_backward(ws):
 
 
 def test_fftn_directional_finite_difference(ws):
-    """L(x) = Re<w, F x> is linear, so central differences are exact up to
-    rounding; compare along random directions."""
+    """L(x) = Re<w, F x> is linear, so a central difference equals the
+    directional derivative for any step; a unit step keeps the FP32 rounding
+    of L (~1e-3 here) from being amplified by 1/(2h).  Random directions."""
     shape = (16, 16, 16)
     x0 = to_dev(synth.normal_c(shape, seed=5))
     w = to_dev(synth.normal_c(shape, seed=6))
@@ -51,7 +52,7 @@ def test_fftn_directional_finite_difference(ws):
         y = ws.FFTn.apply(x, -1)
         return float(np.sum((to_host(y).astype(np.complex128) * np.conj(to_host(w).astype(np.complex128))).real))
 
-    h = 1e-2
+    h = 1.0
     for s in range(4):
         v = to_dev(synth.normal_c(shape, seed=100 + s))
         fd = (L(x0 + h * v) - L(x0 - h * v)) / (2 * h)
@@ -95,8 +96,9 @@ def test_poisson_256_forward_and_gradient(ws):
 
 
 def test_poisson_directional_fd(ws):
-    """Directional central differences (h = 1e-3) of the loss, accumulated in
-    FP64, along smooth bump-field directions."""
+    """Directional central differences of the loss, accumulated in FP64, along
+    smooth bump-field directions.  The solve is linear, so the difference is
+    exact for any step; a unit step keeps FP32 rounding from being amplified."""
     n = 64
     f, w = _poisson_inputs(n, 11)
     ft = torch.from_numpy(f.astype(np.float32)).cuda()
@@ -108,7 +110,7 @@ def test_poisson_directional_fd(ws):
     def L(x):
         return float(np.sum(to_host(ws.poisson_solve(x)).astype(np.float64) * w.astype(np.float32)))
 
-    h = 1e-3
+    h = 1.0
     for s in range(4):
         v = synth.gaussian_bumps(n, 8, 0.1, seed=200 + s)
         v /= np.abs(v).max()
@@ -128,7 +130,7 @@ def test_poisson_per_coordinate_fd_small(ws):
     (ws.poisson_solve(fg) * wt).sum().backward()
     g = to_host(fg.grad)
     rng = np.random.default_rng(0)
-    h = 1e-2
+    h = 1.0   # linear map: exact for any step
     for _ in range(8):
         idx = tuple(int(i) for i in rng.integers(0, n, 3))
         e = torch.zeros_like(ft)

@@ -108,3 +108,63 @@ def test_graph_capture_replays(ws):
         torch.cuda.synchronize()
         for y, e in zip(ys, eager):
             assert torch.equal(y, e), f"replay {rep}"
+
+
+# --- one persistent launch per batch (batch plans) ----------------------------------
+
+def test_batch_plan_96_uneven_one_launch(ws):
+    shapes = synth.batched_shapes(96, seed=3)
+    arrays = synth.batched_arrays(shapes, seed=3)
+    plans = [ws.Plan(nx, ny, nz, "c64", -1) for nx, ny, nz in shapes]
+    xs = [to_dev(a) for a in arrays]
+    ys = [torch.empty_like(x) for x in xs]
+    bp = ws.BatchPlan(plans, xs, ys)
+    assert bp.tiles > 0
+    for rep in range(3):          # counters reset themselves between launches
+        for y in ys:
+            y.fill_(float(rep + 1))
+        bp.execute()
+        torch.cuda.synchronize()
+        assert not bp.timed_out()
+        worst = 0.0
+        for a, y in zip(arrays, ys):
+            worst = max(worst, rel_l2(y.cpu().numpy(), oracle.fftn(a.astype(np.complex64).astype(np.complex128), -1)))
+        print(f"batch plan, launch {rep}: {bp.tiles} tiles, worst rel_l2 {worst:.3e}")
+        assert worst <= TOL
+
+
+def test_batch_plan_adjoint_in_place_and_graph(ws):
+    shapes = [(32, 64, 96), (256, 32, 32), (128, 96, 64), (64, 1, 256), (96, 32, 1)]
+    plans = [ws.Plan(*s, "c64", -1) for s in shapes]
+    arrays = [synth.uniform_c((s[2], s[1], s[0]), seed=40 + i).astype(np.complex64) for i, s in enumerate(shapes)]
+    xs = [to_dev(a) for a in arrays]
+    bp = ws.BatchPlan(plans, xs, xs, adjoint=True)       # in place
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            bp.execute(stream=s)
+    # the input is restored before each replay, so every replay gives the adjoint of the input
+    for rep in range(3):
+        for x, a in zip(xs, arrays):
+            x.copy_(torch.from_numpy(a))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert not bp.timed_out()
+        for x, a in zip(xs, arrays):
+            assert rel_l2(to_host(x), oracle.fftn(a.astype(np.complex128), +1)) <= TOL, f"replay {rep}"
+
+
+def test_batch_plan_rejects_unsupported(ws):
+    p = ws.Plan(512, 512, 1, "c64", -1)          # 512 has no persistent branch
+    x = torch.zeros((512, 512), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ws.WsfftError) as ei:
+        ws.BatchPlan([p], [x], [x.clone()])
+    assert ei.value.status == 2
+    p1, p2 = ws.Plan(32, 32, 1, "c64", -1), ws.Plan(32, 32, 1, "c64", +1)
+    y = torch.zeros((32, 32), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ws.WsfftError) as ei:
+        ws.BatchPlan([p1, p2], [y, y.clone()], [y.clone(), y.clone()])
+    assert ei.value.status == 1
