@@ -27,6 +27,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs, each scaled by what the same counter reads for a plain
+# device copy of known size in the same process (--calibration-copy).  Keyed
+# by the hash of the kernel sources the counters were taken on; any change to
+# those sources makes the figure stale and it is reported as null.
+KERNEL_SOURCES = ["fft_device.hpp", "pass_config.hpp", "pass_inst.inc", "kernels.hpp", "sizes.inc"]
+MEASURED_TRAFFIC = {}   # source hash -> {"kernel": ..., "bytes": ..., "profile": ...}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2209_15040_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 PAPER_512_FP32_GFLOPS = 18.9e3   # CS-2, 512x512 PEs, 959 us (paper, Table 1 and Section 5.3)
 METRIC = "512^3 c2c 3D FFT µs, GFLOP/s, % HBM roofline; FP16/batched/fwd+bwd vs FP32"
 
@@ -248,6 +265,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration for rocprofv3 --pmc runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -261,6 +280,13 @@ def main() -> int:
     torch.cuda.set_device(0)
 
     K, W = args.steps, args.warmup
+    if args.calibration_copy:
+        src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
     head, plan = headline(ws, torch, K, W)
     n = 512
     N = n ** 3
@@ -268,10 +294,15 @@ def main() -> int:
     value = flops(N) / (us * 1e-6) / 1e9
     dom = max(head["passes"], key=lambda p: p["ms"])
     algo_bytes = 2 * N * 8
+    src_hash = kernel_sources_hash()
+    meas = MEASURED_TRAFFIC.get(src_hash)
     roofline = {"bound": "hbm", "achieved": algo_bytes / (dom["ms"] * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": algo_bytes / (dom["ms"] * 1e-3) / HBM_PEAK, "traffic": None,
+                "unit": "GB/s", "frac": algo_bytes / (dom["ms"] * 1e-3) / HBM_PEAK,
+                "traffic": meas["bytes"] if meas else None,
                 "kernel": f"pass {dom['pass']} of {head['plan']}",
-                "algorithmic_bytes_per_launch": algo_bytes}
+                "algorithmic_bytes_per_launch": algo_bytes,
+                "kernel_sources_hash": src_hash,
+                "traffic_source": meas["profile"] if meas else "no counters recorded for these kernel sources"}
     variants = {}
     if not args.no_variants:
         vs = max(5, K // 2)

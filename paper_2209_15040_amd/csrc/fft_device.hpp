@@ -288,6 +288,14 @@ template <class T> using gptr = __attribute__((address_space(1))) T*;
 template <class T> using gcptr = const __attribute__((address_space(1))) T*;
 template <class T> __device__ __forceinline__ gcptr<T> gload_ptr(const void* p) { return (gcptr<T>)p; }
 template <class T> __device__ __forceinline__ gptr<T> gstore_ptr(void* p) { return (gptr<T>)p; }
+// base + 32-bit byte offset: a wave-uniform base stays in scalar registers and
+// the access takes the (scalar base, vector offset) form
+template <class T> __device__ __forceinline__ gcptr<T> gload_at(const char* base, uint32_t off) {
+    return (gcptr<T>)(base + off);
+}
+template <class T> __device__ __forceinline__ gptr<T> gstore_at(char* base, uint32_t off) {
+    return (gptr<T>)(base + off);
+}
 
 
 struct IoC64 {   // complex64: FP32 re, FP32 im
@@ -324,6 +332,28 @@ struct IoC64 {   // complex64: FP32 re, FP32 im
         w.y = v.y;
         __builtin_nontemporal_store(w, gstore_ptr<f32x2>(p) + i);
     }
+    // byte-addressed forms (base + off), one and two elements
+    template <bool NT> static __device__ __forceinline__ float2 ld(const char* b, uint32_t off) {
+        const f32x2 v = NT ? __builtin_nontemporal_load(gload_at<f32x2>(b, off)) : *gload_at<f32x2>(b, off);
+        return make_float2(v.x, v.y);
+    }
+    template <bool NT> static __device__ __forceinline__ void st(char* b, uint32_t off, float2 v) {
+        f32x2 w;
+        w.x = v.x;
+        w.y = v.y;
+        if (NT) __builtin_nontemporal_store(w, gstore_at<f32x2>(b, off));
+        else *gstore_at<f32x2>(b, off) = w;
+    }
+    static __device__ __forceinline__ void ld2_nt(const char* b, uint32_t off, float2& x, float2& y) {
+        const f32x4 v = __builtin_nontemporal_load(gload_at<f32x4>(b, off));
+        x = make_float2(v.x, v.y);
+        y = make_float2(v.z, v.w);
+    }
+    static __device__ __forceinline__ void st2_nt(char* b, uint32_t off, float2 x, float2 y) {
+        f32x4 w;
+        w.x = x.x; w.y = x.y; w.z = y.x; w.w = y.y;
+        __builtin_nontemporal_store(w, gstore_at<f32x4>(b, off));
+    }
 };
 
 struct IoF16 {   // FP16 re, FP16 im
@@ -353,6 +383,23 @@ struct IoF16 {   // FP16 re, FP16 im
         const uint64_t w = (uint64_t)__builtin_bit_cast(uint32_t, __float22half2_rn(a)) |
                            ((uint64_t)__builtin_bit_cast(uint32_t, __float22half2_rn(b)) << 32);
         __builtin_nontemporal_store(w, gstore_ptr<uint64_t>(p) + i / 2);
+    }
+    static __device__ __forceinline__ float2 unpack(uint32_t w) { return __half22float2(__builtin_bit_cast(__half2, w)); }
+    static __device__ __forceinline__ uint32_t pack(float2 v) { return __builtin_bit_cast(uint32_t, __float22half2_rn(v)); }
+    template <bool NT> static __device__ __forceinline__ float2 ld(const char* b, uint32_t off) {
+        return unpack(NT ? __builtin_nontemporal_load(gload_at<uint32_t>(b, off)) : *gload_at<uint32_t>(b, off));
+    }
+    template <bool NT> static __device__ __forceinline__ void st(char* b, uint32_t off, float2 v) {
+        if (NT) __builtin_nontemporal_store(pack(v), gstore_at<uint32_t>(b, off));
+        else *gstore_at<uint32_t>(b, off) = pack(v);
+    }
+    static __device__ __forceinline__ void ld2_nt(const char* b, uint32_t off, float2& x, float2& y) {
+        const uint64_t w = __builtin_nontemporal_load(gload_at<uint64_t>(b, off));
+        x = unpack((uint32_t)w);
+        y = unpack((uint32_t)(w >> 32));
+    }
+    static __device__ __forceinline__ void st2_nt(char* b, uint32_t off, float2 x, float2 y) {
+        __builtin_nontemporal_store((uint64_t)pack(x) | ((uint64_t)pack(y) << 32), gstore_at<uint64_t>(b, off));
     }
 };
 
@@ -390,6 +437,27 @@ struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
         const uint64_t w = (uint64_t)(f32_to_bf16_rne(a.x) | (f32_to_bf16_rne(a.y) << 16)) |
                            ((uint64_t)(f32_to_bf16_rne(b.x) | (f32_to_bf16_rne(b.y) << 16)) << 32);
         __builtin_nontemporal_store(w, gstore_ptr<uint64_t>(p) + i / 2);
+    }
+    static __device__ __forceinline__ float2 unpack(uint32_t w) {
+        return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+    }
+    static __device__ __forceinline__ uint32_t pack(float2 v) {
+        return f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
+    }
+    template <bool NT> static __device__ __forceinline__ float2 ld(const char* b, uint32_t off) {
+        return unpack(NT ? __builtin_nontemporal_load(gload_at<uint32_t>(b, off)) : *gload_at<uint32_t>(b, off));
+    }
+    template <bool NT> static __device__ __forceinline__ void st(char* b, uint32_t off, float2 v) {
+        if (NT) __builtin_nontemporal_store(pack(v), gstore_at<uint32_t>(b, off));
+        else *gstore_at<uint32_t>(b, off) = pack(v);
+    }
+    static __device__ __forceinline__ void ld2_nt(const char* b, uint32_t off, float2& x, float2& y) {
+        const uint64_t w = __builtin_nontemporal_load(gload_at<uint64_t>(b, off));
+        x = unpack((uint32_t)w);
+        y = unpack((uint32_t)(w >> 32));
+    }
+    static __device__ __forceinline__ void st2_nt(char* b, uint32_t off, float2 x, float2 y) {
+        __builtin_nontemporal_store((uint64_t)pack(x) | ((uint64_t)pack(y) << 32), gstore_at<uint64_t>(b, off));
     }
 };
 
@@ -561,19 +629,35 @@ struct PencilPass {
         }
     };
 
+    // Per-thread context of one tile.  Besides the element indices, the
+    // split form of the addresses: element e of this thread's pencil or
+    // column is at ib + (e - le_in) * ies + il (bytes), where ib and ies are
+    // the same for the whole wave and il is a 32-bit per-lane offset; le_in
+    // is the part of e that varies across the wave's lanes (j, or j * NB for
+    // paired slots).  Likewise ob, oes, ol for the stored elements.  Lanes of
+    // a ragged tile past the last pencil or column load the tile's first one
+    // instead (it always exists; pencils are independent and such lanes
+    // never store), so split loads need no per-element predicate.  split is
+    // false when a lane offset could exceed 32 bits (strides of several GiB);
+    // the 64-bit element-index form is used then.
     struct Ctx {
         int p, j;
         bool valid;
+        bool split;
         int64_t col;          // global column (strided) or pencil (contiguous)
         int64_t o1;
         int64_t base_in, base_out;
+        const char* ib;
+        char* ob;
+        int64_t ies, oes;
+        uint32_t il, ol;
     };
 
     // Twiddle table entry: in LDS for persistent kernels, else in global memory.
     __device__ __forceinline__ static float2 tw_at(const float2* tw, int i) {
         if constexpr (PERSIST) return tw[i];
         else {
-            const f32x2 w = gload_ptr<f32x2>(tw)[i];
+            const f32x2 w = *gload_at<f32x2>(reinterpret_cast<const char*>(tw), (uint32_t)i * 8u);
             return make_float2(w.x, w.y);
         }
     }
@@ -725,6 +809,28 @@ struct PencilPass {
             }
             return;
         }
+        if (c.split) {
+            if constexpr (pairable<S>()) {
+                if (((reinterpret_cast<uintptr_t>(c.ob) + c.ol) & (2 * IO::bytes - 1)) == 0) {
+#pragma unroll
+                    for (int t = 0; t < Q::NB; t += 2)
+#pragma unroll
+                        for (int r = 0; r < Q::R; ++r)
+                            IO::st2_nt(c.ob + (int64_t)eoff<S>(t, r) * c.oes, c.ol, cscale(v[t * Q::R + r], a.scale),
+                                       cscale(v[(t + 1) * Q::R + r], a.scale));
+                    return;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < Q::NB; ++t) {
+                const int b = Q::bf(c.j, t);
+                if (!Q::FULL && b >= Q::NBF) continue;
+#pragma unroll
+                for (int r = 0; r < Q::R; ++r)
+                    IO::template st<NT>(c.ob + (int64_t)eoff<S>(t, r) * c.oes, c.ol, cscale(v[t * Q::R + r], a.scale));
+            }
+            return;
+        }
         if constexpr (pairable<S>()) {
             if (pair_aligned(a.dst, c.base_out)) {
 #pragma unroll
@@ -772,17 +878,30 @@ struct PencilPass {
     __device__ __forceinline__ static Ctx make_ctx(const PassArgs& a, int64_t t) {
         const int tid = threadIdx.x;
         Ctx c;
+        constexpr int64_t B = IO::bytes;
         if constexpr (STRIDED) {
+            const int wave = __builtin_amdgcn_readfirstlane(tid) >> 6;   // wave-uniform
             c.p = tid % P;
             c.j = tid / P;
             const int64_t ctiles = (a.C + P - 1) / P;
             const int64_t rest = t / ctiles;
-            c.col = (t - rest * ctiles) * P + c.p;
+            const int64_t col0 = (t - rest * ctiles) * P;
+            c.col = col0 + c.p;
             c.o1 = rest % a.O1;
             const int64_t o2 = rest / a.O1;
             c.valid = c.col < a.C;
             c.base_in = c.col + c.o1 * a.os1_in + o2 * a.os2_in;
             c.base_out = c.col * a.cs_out + c.o1 * a.os1_out + o2 * a.os2_out;
+            // the wave's lanes hold rows jw .. jw + JS - 1 (j grows with tid)
+            constexpr int JS = (64 + P - 1) / P + 1;
+            const int jw = (wave * 64) / P, jl = c.j - jw;
+            c.ies = a.es_in * B;
+            c.oes = a.es_out * B;
+            c.ib = static_cast<const char*>(a.src) + (col0 + c.o1 * a.os1_in + o2 * a.os2_in + jw * a.es_in) * B;
+            c.ob = static_cast<char*>(a.dst) + (col0 * a.cs_out + c.o1 * a.os1_out + o2 * a.os2_out + jw * a.es_out) * B;
+            c.il = (uint32_t)(((c.valid ? c.p : 0) + jl * a.es_in) * B);
+            c.ol = (uint32_t)((c.p * a.cs_out + jl * a.es_out) * B);
+            c.split = (P * B + JS * c.ies) < (int64_t(1) << 32) && (P * a.cs_out * B + JS * c.oes) < (int64_t(1) << 32);
         } else {
             c.j = tid % T;
             c.p = tid / T;
@@ -791,11 +910,27 @@ struct PencilPass {
             c.valid = c.col < a.C;
             c.base_in = c.col * a.os1_in;
             c.base_out = c.col * a.os1_out;
+            // bases at the tile's first pencil
+            constexpr int m0 = PAIRS ? St<0>::NB : 1, mL = PAIRS ? St<NS - 1>::NB : 1;
+            c.ies = B;
+            c.oes = B;
+            c.ib = static_cast<const char*>(a.src) + t * P * a.os1_in * B;
+            c.ob = static_cast<char*>(a.dst) + t * P * a.os1_out * B;
+            c.il = (uint32_t)(((c.valid ? c.p : 0) * a.os1_in + c.j * m0) * B);
+            c.ol = (uint32_t)((c.p * a.os1_out + c.j * mL) * B);
+            c.split = (P * a.os1_in + N) * B < (int64_t(1) << 32) && (P * a.os1_out + N) * B < (int64_t(1) << 32);
         }
         return c;
     }
 
     static constexpr int V0 = St<0>::NB * St<0>::R;   // first-stage inputs per thread
+
+    // Whether the contiguous layout's first stage can move its inputs in
+    // pairs (decided on the unpaired instance: the butterfly counts are the
+    // same under both mappings).
+    static constexpr bool pairs_help() {
+        return !STRIDED && NT && St<0>::FULL && St<0>::NB % 2 == 0 && St<0>::NBF % 2 == 0;
+    }
 
     // First-stage inputs straight from HBM.
     // Paired accesses: thread slots t and t+1 hold adjacent elements.
@@ -806,8 +941,36 @@ struct PencilPass {
         return ((reinterpret_cast<uintptr_t>(p) & (2 * IO::bytes - 1)) == 0) && (base % 2 == 0);
     }
 
+    // Element offset of slot (t, r) of stage S relative to the lane's own
+    // part: e = b + r*NBF with b = j + t*T (or j*NB + t when paired).
+    template <int S> static constexpr int eoff(int t, int r) {
+        return PAIRS ? t + r * St<S>::NBF : t * T + r * St<S>::NBF;
+    }
+
     __device__ __forceinline__ static void load_first(float2* v, const Ctx& c, const PassArgs& a) {
         using Q = St<0>;
+        if (c.split) {
+            if constexpr (pairable<0>()) {
+                if (((reinterpret_cast<uintptr_t>(c.ib) + c.il) & (2 * IO::bytes - 1)) == 0) {
+#pragma unroll
+                    for (int t = 0; t < Q::NB; t += 2)
+#pragma unroll
+                        for (int r = 0; r < Q::R; ++r)
+                            IO::ld2_nt(c.ib + (int64_t)eoff<0>(t, r) * c.ies, c.il, v[t * Q::R + r],
+                                       v[(t + 1) * Q::R + r]);
+                    return;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < Q::NB; ++t) {
+                const int b = Q::bf(c.j, t);
+                if (!Q::FULL && b >= Q::NBF) continue;
+#pragma unroll
+                for (int r = 0; r < Q::R; ++r)
+                    v[t * Q::R + r] = IO::template ld<NT>(c.ib + (int64_t)eoff<0>(t, r) * c.ies, c.il);
+            }
+            return;
+        }
         if constexpr (pairable<0>()) {
             if (c.valid && pair_aligned(a.src, c.base_in)) {
 #pragma unroll

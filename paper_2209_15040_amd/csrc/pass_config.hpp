@@ -3,15 +3,17 @@
 //   T  threads per pencil          P  pencils (contiguous layout) or
 //   K  LDS exchange rounds            columns (strided layout) per workgroup
 //
-// Rules measured on MI355X at N = 512 (512^3 complex64):
-// * strided tiles need rows of >= 256 bytes (32 complex64 columns, 64 of
-//   the 4-byte types): 128-byte rows run the 2 MiB-stride pass at ~44% of
-//   the copy rate of 256-byte rows;
-// * 32 elements per thread with the exchange split into rounds of <= ~34 KB
-//   keeps two or more workgroups resident per CU, so one workgroup's
-//   transform and store drain overlap another's loads;
-// * contiguous pencils run best with 16 elements per thread and 256-thread
-//   workgroups;
+// Rules measured on MI355X at N = 512 (512^3 arrays):
+// * strided tiles of 32 columns: 256-byte rows for complex64, 128-byte rows
+//   for the 4-byte types (these carry half the bytes and do better with
+//   narrower tiles than with 64 columns);
+// * strided complex64 tiles run best with radix <= 16 stages (plan 1), the
+//   4-byte types with the fewest stages (plan 0);
+// * 32 elements per thread, the exchange split into rounds of up to ~72 KB
+//   of LDS, so two workgroups stay resident per CU and one's transform and
+//   store drain overlap the other's loads;
+// * contiguous pencils: 16 elements per thread, 256-thread workgroups, and
+//   paired (two-element) first-stage loads where the stage allows them;
 // * non-temporal (streaming) loads and stores help every pass.
 #pragma once
 #include "fft_device.hpp"
@@ -19,8 +21,14 @@
 namespace wsfft {
 
 constexpr int kLdsBytesMax = 160 * 1024;   // LDS per CU on gfx950
-constexpr int kLdsRoundBudget = 36 * 1024; // target LDS per strided workgroup
+constexpr int kLdsRoundBudget = 36 * 1024; // LDS per exchange round, 256-thread strided tiles
 constexpr int kPassFlags = kFlagNontemporal;
+
+// Radix plan of the default strided kernel (see make_radices).
+constexpr int cfg_plan_strided(int N, int bytes) {
+    (void)N;
+    return bytes == 8 ? 1 : 0;
+}
 
 constexpr int cfg_T_contig(int N, int plan = 0) {
     int t = N / 16;
@@ -53,18 +61,22 @@ constexpr int cfg_T_strided(int N, int bytes, int plan = 0) {
     return t < 1 ? 1 : t;
 }
 constexpr int cfg_P_strided(int N, int bytes, int plan = 0) {
-    int p = bytes == 8 ? 32 : 64;
+    (void)bytes;
+    int p = 32;
     if (N <= 64) p = 64;                   // one full wave of columns at least
     const int cap = pow2_floor(1024 / cfg_T_strided(N, bytes, plan));
     return p > cap ? cap : p;
 }
-// Smallest K dividing N whose exchange round fits the LDS budget; when that
-// takes more than 8 rounds, accept up to twice the budget instead.
+// Smallest K dividing N whose exchange round fits the LDS budget (twice the
+// per-round budget for workgroups of up to 512 threads, two of which still
+// fit per CU); when that takes more than 8 rounds, accept up to twice the
+// budget instead.
 constexpr int cfg_K_strided(int N, int bytes, int plan = 0) {
     const int p = cfg_P_strided(N, bytes, plan);
+    const int budget = cfg_T_strided(N, bytes, plan) * p <= 512 ? 2 * kLdsRoundBudget : kLdsRoundBudget;
     int first = 0;
     for (int k = 1; k <= N && !first; ++k)
-        if (N % k == 0 && (N / k) * (p + 1) * 8 <= kLdsRoundBudget) first = k;
+        if (N % k == 0 && (N / k) * (p + 1) * 8 <= budget) first = k;
     if (first && first <= 8) return first;
     for (int k = 1; k <= N; ++k)
         if (N % k == 0 && (N / k) * (p + 1) * 8 <= 2 * kLdsRoundBudget) return k;

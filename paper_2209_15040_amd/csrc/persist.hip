@@ -130,7 +130,9 @@ __global__ __launch_bounds__(kPT) void persist_kernel(const PersistPass* __restr
         __syncthreads();
         const int pi = __builtin_amdgcn_readfirstlane(s_pass);
         if (pi < 0) break;
-        const int64_t item = s_item;
+        const int64_t iv = s_item;   // broadcast through registers: the tile index stays wave-uniform
+        const int64_t item = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(iv >> 32)) << 32) |
+                                       (uint32_t)__builtin_amdgcn_readfirstlane((int)iv));
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the previous superstep
         const PersistPass& P = passes[pi];
         run_type<SIGN>(P.type, P.a, item - P.first, lds_dyn);
