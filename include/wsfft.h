@@ -161,8 +161,9 @@ wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const 
  * plan is used), checks every entry, uploads a table of the supersteps of all
  * arrays and allocates the batch plan's own completion counters.
  * wsfft_batch_execute then enqueues one launch of a resident grid that walks
- * every tile of every pass of every array; a tile of superstep L of an array
- * starts once all tiles of superstep L-1 of that array are done.  No host
+ * every tile of every pass of every array in superstep order; tiles of
+ * superstep L start once all tiles of superstep L-1 (of every array) are
+ * done, a grid-wide barrier per superstep inside the one launch.  No host
  * copies or allocations happen in execute, so it can be captured in a HIP
  * graph.  A batch plan must not run concurrently with itself (its counters
  * are shared by its launches).  Supported: WSFFT_C64 plans whose axes are 32,

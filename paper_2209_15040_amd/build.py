@@ -38,13 +38,21 @@ def _headers_mtime() -> float:
     return max(os.path.getmtime(h) for h in hs)
 
 
+# Per-file additions.  persist.hip: its single-lane ticket atomics are claimed
+# one tile ahead; the wave-reduction rewrite of uniform atomics would wait for
+# each result at once and undo that.
+EXTRA_FLAGS = {
+    "persist.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+}
+
+
 def _compile(src: str, incremental: bool, hdr_mtime: float) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if incremental and os.path.exists(obj):
         t = os.path.getmtime(obj)
         if t >= os.path.getmtime(src) and t >= hdr_mtime:
             return obj
-    cmd = [HIPCC, *CXXFLAGS, "-c", src, "-o", obj + ".tmp"]
+    cmd = [HIPCC, *CXXFLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the packed-fp32 feature and says so
     noise = ("packed-fp32-ops", "is not a recognized feature for this target", "(ignoring feature)")

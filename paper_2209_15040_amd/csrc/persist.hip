@@ -1,15 +1,21 @@
 // One persistent launch for a whole batch of transforms.
 //
-// The work of a batch is a list of passes (one per array and superstep, in
-// superstep-major order), each split into tiles.  Workgroups of a resident
-// grid claim tiles in list order from a ticket counter; a tile of superstep
-// L > 0 of an array first waits until every tile of superstep L-1 of the same
-// array has been published.  Claim order makes this deadlock-free whether or
-// not all workgroups are resident at once: a claimed tile depends only on
-// tiles claimed earlier, by workgroups that are already running, whose own
-// dependencies were claimed earlier still.  The wait is bounded; on timeout the
-// launch records an error and finishes.  The last workgroup to leave resets
-// the counters, so the next launch on the same counters starts from zero.
+// The work of a batch is a list of passes (one per array and superstep), in
+// superstep-major order, each split into tiles.  Workgroups of a resident
+// grid claim tiles in list order from a ticket counter.  Synchronisation is
+// per superstep level: a workgroup counts the tiles it finishes and publishes
+// them (one release, one counter add) only when its next ticket belongs to a
+// higher level or when it leaves; at its first tile of level L > 0 it waits
+// until every tile of level L-1 has been published, then acquires once.  The
+// cache-wide write-back and invalidate that release and acquire cost across
+// the XCDs' separate L2s thus happen a few times per workgroup, not per tile.
+// Claim order makes the wait deadlock-free whether or not all workgroups are
+// resident at once: a workgroup waits only after publishing everything it
+// holds, and every earlier tile belongs to a running workgroup that will
+// publish it when it claims its next ticket or leaves.  The wait is bounded;
+// on timeout the launch records an error and finishes.  The last workgroup to
+// leave resets the counters, so the next launch on the same counters starts
+// from zero.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -25,7 +31,8 @@ constexpr int kPersistFlags = kPassFlags;
 // Geometry in the persistent kernel: one butterfly of the widest radix per
 // thread and exactly kPersistThreads threads per workgroup.
 template <int N, bool ST> struct PGeo {
-    static constexpr int T = N / max_radix(make_radices(N, 0));
+    static constexpr int PLAN = 0;
+    static constexpr int T = N / max_radix(make_radices(N, PLAN));
     static constexpr int P = kPT / T;
     static_assert(T * P == kPT, "persistent geometry must fill the workgroup");
     static constexpr int kfor() {
@@ -35,7 +42,7 @@ template <int N, bool ST> struct PGeo {
         return N;
     }
     static constexpr int K = kfor();
-    template <int SIGN> using PP = PencilPass<N, T, P, ST, IoC64, SIGN, kPersistFlags, K, 0>;
+    template <int SIGN> using PP = PencilPass<N, T, P, ST, IoC64, SIGN, kPersistFlags, K, PLAN>;
 };
 
 // The lengths of the uneven-batch workload (axes of 32, 64, 96, 128, 256) in
@@ -70,44 +77,62 @@ __device__ __forceinline__ unsigned load_acquire(const unsigned* p) {
 }
 
 // Control flow is kept wave-uniform: wave 0 claims (lane 0 issues the atomics,
-// readfirstlane broadcasts), every other branch depends on values read back
-// through readfirstlane, and one lane-0 region per iteration both publishes the
-// previous tile and claims the next.  Two separate lane-0 regions, one at each
-// end of the loop body, can be joined by the compiler across the back edge into
-// a nested loop that leaves lane 0 parked while the other lanes keep cycling
-// through the barriers.  The iteration cap bounds the loop whatever shape it
-// is compiled to.
+// readfirstlane broadcasts) and every branch depends on values read back
+// through readfirstlane.  Lane-0 regions hold no barrier and no back edge of
+// the loop: two such regions at both ends of a loop body can be joined by the
+// compiler across the back edge into a nested loop that parks lane 0 while
+// the other lanes keep cycling through the barriers.  The iteration cap
+// bounds the loop whatever shape it is compiled to.
 template <int SIGN>
-__global__ __launch_bounds__(kPT) void persist_kernel(const PersistPass* __restrict__ passes, int npasses,
-                                                      int64_t total, PersistCounters* ctr, unsigned spin_limit) {
+__global__ __launch_bounds__(kPT, 2) void persist_kernel(const PersistPass* __restrict__ passes, int npasses,
+                                                      PersistLevels lv, PersistCounters* ctr, unsigned spin_limit) {
     extern __shared__ float2 lds_dyn[];
     __shared__ int64_t s_item;
     __shared__ int s_pass;
     const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;   // wave-uniform
     const bool lane0 = threadIdx.x == 0;
-    int prev = -1;                 // pass of the tile finished in the previous iteration
+    const int64_t total = lv.end[lv.count - 1];
+    int level = -1;          // level of the tiles finished since the last publication
+    unsigned pending = 0;    // those tiles
+    unsigned next = 0;       // lane 0 of wave 0: the ticket claimed ahead
+    bool have_next = false;
+    int cur = 0;             // wave 0: pass of the last item (items only grow)
     for (int64_t iter = 0; iter <= total; ++iter) {
         if (wave0) {
             unsigned got = 0;
-            if (lane0) {
-                if (prev >= 0) __hip_atomic_fetch_add(&ctr->done[prev], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                got = atomicAdd(&ctr->ticket, 1u);
-            }
+            if (lane0) got = have_next ? next : atomicAdd(&ctr->ticket, 1u);
             const int64_t item = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)got);
             int pi = -1;
-            if (item < total) {   // the pass holding this item (passes sorted by `first`)
-                int lo = 0, hi = npasses - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) / 2;
-                    if (passes[mid].first <= item) lo = mid;
-                    else hi = mid - 1;
-                }
-                pi = lo;
-                const int dep = passes[pi].dep;
-                if (dep >= 0) {   // bounded wait for the previous superstep of this array
-                    const unsigned need = (unsigned)passes[dep].tiles;
+            if (item < total) {
+                // the pass holding this item (passes sorted by `first`)
+                while (cur + 1 < npasses && passes[cur + 1].first <= item) ++cur;
+                pi = cur;
+                // claim the following ticket now; its latency hides behind this tile.
+                // A held ticket is never of a lower level than the current one,
+                // so waiting for the previous level cannot depend on it.
+                if (lane0) next = atomicAdd(&ctr->ticket, 1u);
+            }
+            have_next = true;
+            if (lane0) {
+                s_item = item;
+                s_pass = pi;
+            }
+        }
+        __syncthreads();
+        const int pi = __builtin_amdgcn_readfirstlane(s_pass);
+        const int L = pi < 0 ? kPersistMaxLevels : __builtin_amdgcn_readfirstlane(passes[pi].level);
+        if (L != level) {
+            if (pending != 0) {   // publish the finished tiles of `level`
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __syncthreads();
+                if (lane0) __hip_atomic_fetch_add(&ctr->done[level], pending, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                pending = 0;
+            }
+            if (L > 0 && L < kPersistMaxLevels) {   // bounded wait for the whole previous level
+                if (wave0) {
+                    const unsigned need = (unsigned)(lv.end[L - 1] - (L >= 2 ? lv.end[L - 2] : 0));
                     for (unsigned spins = 0;; ++spins) {
-                        const unsigned have = __builtin_amdgcn_readfirstlane(load_acquire(&ctr->done[dep]));
+                        const unsigned have = __builtin_amdgcn_readfirstlane(load_acquire(&ctr->done[L - 1]));
                         if (have >= need) break;
                         // give up after spin_limit polls, or at once after
                         // another workgroup has given up
@@ -121,30 +146,25 @@ __global__ __launch_bounds__(kPT) void persist_kernel(const PersistPass* __restr
                         __builtin_amdgcn_s_sleep(2);
                     }
                 }
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the previous level
             }
-            if (lane0) {
-                s_item = item;
-                s_pass = pi;
-            }
+            level = L;
         }
-        __syncthreads();
-        const int pi = __builtin_amdgcn_readfirstlane(s_pass);
         if (pi < 0) break;
         const int64_t iv = s_item;   // broadcast through registers: the tile index stays wave-uniform
         const int64_t item = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(iv >> 32)) << 32) |
                                        (uint32_t)__builtin_amdgcn_readfirstlane((int)iv));
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the previous superstep
         const PersistPass& P = passes[pi];
         run_type<SIGN>(P.type, P.a, item - P.first, lds_dyn);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this tile before its publication
-        __syncthreads();                           // every thread's stores fenced; LDS free
-        prev = pi;
+        __syncthreads();   // LDS and the shared slots free for the next tile
+        ++pending;
     }
     // last workgroup out resets the counters for the next launch
     if (lane0) {
         const unsigned prevf = __hip_atomic_fetch_add(&ctr->finished, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (prevf + 1 == gridDim.x) {
-            for (int i = 0; i < npasses; ++i) ctr->done[i] = 0;
+            for (int i = 0; i < kPersistMaxLevels; ++i) ctr->done[i] = 0;
             ctr->ticket = 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(&ctr->finished, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -184,13 +204,13 @@ hipError_t persist_prepare(int* blocks_per_cu) {
     return e;
 }
 
-hipError_t persist_launch(int sign, const PersistPass* passes, int npasses, int64_t total, PersistCounters* ctr,
-                          unsigned grid, unsigned spin_limit, hipStream_t s) {
+hipError_t persist_launch(int sign, const PersistPass* passes, int npasses, const PersistLevels& levels,
+                          PersistCounters* ctr, unsigned grid, unsigned spin_limit, hipStream_t s) {
     if (sign < 0)
-        hipLaunchKernelGGL(persist_kernel<-1>, dim3(grid), dim3(kPT), kPersistLds, s, passes, npasses, total, ctr,
+        hipLaunchKernelGGL(persist_kernel<-1>, dim3(grid), dim3(kPT), kPersistLds, s, passes, npasses, levels, ctr,
                            spin_limit);
     else
-        hipLaunchKernelGGL(persist_kernel<1>, dim3(grid), dim3(kPT), kPersistLds, s, passes, npasses, total, ctr,
+        hipLaunchKernelGGL(persist_kernel<1>, dim3(grid), dim3(kPT), kPersistLds, s, passes, npasses, levels, ctr,
                            spin_limit);
     return hipGetLastError();
 }

@@ -7,13 +7,22 @@ namespace wsfft {
 
 constexpr int kPersistThreads = 256;
 
+constexpr int kPersistMaxLevels = 4;   // supersteps per array
+
 // One superstep of one array.
 struct PersistPass {
     PassArgs a;          // resolved arguments (buffers, geometry, scale)
     int64_t first;       // index of its first tile in the launch's work list
     int64_t tiles;
     int32_t type;        // kernel branch (persist_type)
-    int32_t dep;         // pass that must be complete first, or -1
+    int32_t level;       // superstep index; the work list is level-major
+};
+
+// Tiles of each level: level L holds work items [end[L-1], end[L]).
+struct PersistLevels {
+    int64_t end[kPersistMaxLevels];
+    int32_t count;
+    int32_t pad;
 };
 
 // Device-resident counters owned by one batch plan.
@@ -22,14 +31,14 @@ struct PersistCounters {
     unsigned finished;   // workgroups that left
     unsigned error;      // nonzero: a dependency wait timed out
     unsigned pad;
-    unsigned done[1];    // tiles published per pass (npasses entries)
+    unsigned done[kPersistMaxLevels];   // tiles published per level
 };
 
 int persist_type(int n, bool strided);        // -1: no persistent kernel for it
 int persist_per_block(int n, bool strided);   // pencils or columns per workgroup
 int persist_lds_bytes();
 hipError_t persist_prepare(int* blocks_per_cu);
-hipError_t persist_launch(int sign, const PersistPass* passes, int npasses, int64_t total, PersistCounters* ctr,
-                          unsigned grid, unsigned spin_limit, hipStream_t s);
+hipError_t persist_launch(int sign, const PersistPass* passes, int npasses, const PersistLevels& levels,
+                          PersistCounters* ctr, unsigned grid, unsigned spin_limit, hipStream_t s);
 
 }  // namespace wsfft

@@ -879,6 +879,7 @@ struct wsfft_batch_plan_s {
     int sign;                  // effective kernel sign of every pass
     int npasses;
     int64_t total;             // work items (tiles) of one execution
+    wsfft::PersistLevels levels;
     unsigned grid;
     wsfft::PersistPass* d_passes = nullptr;
     wsfft::PersistCounters* d_ctr = nullptr;
@@ -922,11 +923,12 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
                 return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
         maxp = std::max(maxp, p->passes.size());
     }
-    // superstep-major list of passes; dep = same array, previous superstep
+    if (maxp > (size_t)kPersistMaxLevels) return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+    // superstep-major list of passes
     std::vector<PersistPass> list;
-    std::vector<int> last(count, -1);
+    PersistLevels levels{};
     int64_t total = 0;
-    for (size_t pi = 0; pi < maxp; ++pi)
+    for (size_t pi = 0; pi < maxp; ++pi) {
         for (int i = 0; i < count; ++i) {
             const wsfft_plan_s* p = plans[i];
             if (pi >= p->passes.size()) continue;
@@ -941,12 +943,14 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
             const int64_t per = persist_per_block((int)P.n, P.strided);
             q.tiles = P.strided ? ((q.a.C + per - 1) / per) * q.a.O1 * q.a.O2 : (q.a.C + per - 1) / per;
             q.type = persist_type((int)P.n, P.strided);
-            q.dep = last[i];
+            q.level = (int32_t)pi;
             q.first = total;
             total += q.tiles;
-            last[i] = (int)list.size();
             list.push_back(q);
         }
+        levels.end[pi] = total;
+        levels.count = (int32_t)pi + 1;
+    }
     // tickets are 32-bit and every workgroup draws one past the end
     if (list.empty() || total > 0x7fffffffLL) return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
     wsfft_batch_plan_s* b = new (std::nothrow) wsfft_batch_plan_s();
@@ -955,6 +959,7 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
     b->sign = sign;
     b->npasses = (int)list.size();
     b->total = total;
+    b->levels = levels;
     int per_cu = 0, cus = 0;
     if (persist_prepare(&per_cu) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
@@ -962,7 +967,7 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
         return batch_fail(WSFFT_ERROR_HIP);
     }
     b->grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(total, (int64_t)std::max(1, per_cu) * cus));
-    const size_t ctr_bytes = sizeof(PersistCounters) + sizeof(unsigned) * (size_t)list.size();
+    const size_t ctr_bytes = sizeof(PersistCounters);
     if (hipMalloc(&b->d_passes, sizeof(PersistPass) * list.size()) != hipSuccess) {
         delete b;
         return batch_fail(WSFFT_ERROR_OUT_OF_MEMORY);
@@ -996,7 +1001,7 @@ wsfft_status_t wsfft_batch_execute(wsfft_batch_plan_t b, hipStream_t stream) {
     if (cur != b->device) return WSFFT_ERROR_WRONG_DEVICE;
     // a dependency wait gives up after 2^22 polls (well under a second per
     // wait, far beyond any tile's duration): a bug cannot hang the GPU
-    return wsfft::persist_launch(b->sign, b->d_passes, b->npasses, b->total, b->d_ctr, b->grid, 1u << 22, stream) ==
+    return wsfft::persist_launch(b->sign, b->d_passes, b->npasses, b->levels, b->d_ctr, b->grid, 1u << 22, stream) ==
                    hipSuccess
                ? WSFFT_SUCCESS
                : WSFFT_ERROR_HIP;
