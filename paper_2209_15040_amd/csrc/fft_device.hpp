@@ -242,6 +242,7 @@ constexpr int best_max(int N, int s, int rmax) {
 // Radix schedules: plan 0 allows radices up to 32 (fewest stages, most
 // registers), plan 1 up to 16, plan 2 up to 8.
 constexpr int plan_rmax(int plan) { return plan == 0 ? 32 : (plan == 1 ? 16 : 8); }
+constexpr int kTwPlans = 3;   // radix plans 0, 1, 2
 
 // Stage radices of a length N = 2^a 3^b: the fewest stages allowed by the
 // plan's largest radix, then the most even split; ascending order.
@@ -276,6 +277,17 @@ constexpr int stage_ns(const Radices& R, int s) {
     int p = 1;
     for (int i = 0; i < s; ++i) p *= R.r[i];
     return p;
+}
+
+// Stage twiddle table of a radix plan: for every stage s >= 1 (radix R,
+// sub-length Ns) a block of (R - 1) * Ns entries, entry (r - 1) * Ns + k
+// holding W_{Ns*R}^{k*r}, blocks in stage order.  Lanes that take
+// consecutive butterflies (consecutive k) read consecutive entries.  The
+// blocks fill N - R_0 < N entries; tables are allotted N.
+constexpr int stage_tw_offset(const Radices& R, int s) {
+    int off = 0;
+    for (int i = 1; i < s; ++i) off += (R.r[i] - 1) * stage_ns(R, i);
+    return off;
 }
 
 // --------------------------------------------------------- storage types ---
@@ -497,13 +509,14 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
 struct PassArgs {
     const void* src;
     void* dst;
-    const float2* tw;     // W_N^m = exp(-2*pi*i*m/N), m in [0, N)
-    const float2* tw4;    // four-step twiddles W_M^m, m in [0, M), or null
+    const float2* tw;     // stage twiddles of the kernel's radix plan (stage_tw_offset), N entries
+    const float2* tw4;    // four-step twiddles (M entries, see tw4_mode), or null
     int64_t M;            // full axis length for tw4
     int64_t C, O1, O2;
     int64_t es_in, os1_in, os2_in;
     int64_t es_out, cs_out, os1_out, os2_out;
-    int32_t tw4_mode;     // 0: none; 1: output e of column c times W_M^(c*e); 2: W_M^(o1*e)
+    int32_t tw4_mode;     // 0: none; 1: output e of column c times W_M^(c*e), table entry c*N + e;
+                          // 2: times W_M^(o1*e), table entry o1*e
     int32_t tstore;       // strided layout only: store columns as contiguous runs via LDS
     float scale;          // multiplies every stored value
 };
@@ -672,9 +685,10 @@ struct PencilPass {
             float2* u = v + t * Q::R;
             if (S > 0) {
                 const int k = b % Q::Ns;
+                constexpr int off = stage_tw_offset(RD, S);
 #pragma unroll
                 for (int r = 1; r < Q::R; ++r) {
-                    float2 w = tw_at(tw, k * r * Q::TWS);
+                    float2 w = tw_at(tw, off + (r - 1) * Q::Ns + k);
                     if (SIGN > 0) w.y = -w.y;
                     u[r] = cmul(u[r], w);
                 }
@@ -723,11 +737,14 @@ struct PencilPass {
         }
     }
 
-    // Four-step twiddle of output element e (tw4_mode != 0).  g < M/N and
-    // e < N, so g*e < M: no reduction needed.
+    // Four-step twiddle W_M^{g*e} of output element e (tw4_mode != 0); g < M/N
+    // and e < N, so g*e < M.  Mode 1 (g = column) reads the table laid out by
+    // output position, entry g*N + e, so lanes with consecutive e read
+    // consecutive entries; mode 2 (g = o1, the same for the whole tile) reads
+    // the plain table W_M^m at m = g*e.
     __device__ __forceinline__ static float2 tw4_of(int e, int64_t col, int64_t o1, const PassArgs& a) {
-        const int64_t g = a.tw4_mode == 1 ? col : o1;
-        const f32x2 wv = gload_ptr<f32x2>(a.tw4)[g * e];
+        const int64_t m = a.tw4_mode == 1 ? col * N + e : o1 * e;
+        const f32x2 wv = gload_ptr<f32x2>(a.tw4)[m];
         float2 w = make_float2(wv.x, wv.y);
         if (SIGN > 0) w.y = -w.y;
         return w;

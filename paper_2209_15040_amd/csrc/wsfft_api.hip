@@ -307,6 +307,11 @@ std::string tune_key(const wsfft_plan_s* plan, const Pass& P, const char* arch) 
     return buf;
 }
 
+// The stage twiddles of the radix plan of P's kernel (kStage table block).
+void set_stage_tw(const wsfft_plan_s* plan, Pass& P) {
+    P.args.tw = plan->tw_dev + P.tw_off + (int64_t)P.kern_neg->plan * P.n;
+}
+
 bool use_variant(wsfft_plan_s* plan, Pass& P, int v) {
     const StorageKind kind = kind_of(plan->dtype);
     const PassKernel* kn = find_pass_kernel(kind, -1, (int)P.n, P.strided, P.four_step == 1, v);
@@ -318,6 +323,7 @@ bool use_variant(wsfft_plan_s* plan, Pass& P, int v) {
     P.kern_pos = kp;
     P.variant = v;
     P.grid = dim3((unsigned)blocks);
+    set_stage_tw(plan, P);
     return true;
 }
 
@@ -480,15 +486,25 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     std::vector<AxisGeo> order = split;   // split axes first: pass A reads the input
     order.insert(order.end(), direct.begin(), direct.end());
 
-    // twiddle tables: (length, offset) for every distinct length
-    std::vector<std::pair<int64_t, int64_t>> tables;
+    // twiddle tables, one per distinct (kind, length, n1):
+    //  kStage: the stage tables of the radix plans 0, 1, 2 of a pass length,
+    //          len entries each (stage_tw_offset); a pass uses the block of
+    //          its kernel's plan;
+    //  kPlain: entry m is W_len^m (inter-pass twiddles of strided split axes);
+    //  kMatrix: entry m is W_len^{(m div n1) * (m mod n1)}, the inter-pass
+    //          twiddle of output position k1 + n1*y2 of pass A of a
+    //          unit-stride split axis, so lanes that store consecutive outputs
+    //          read consecutive entries.
+    enum { kStage = 0, kPlain = 1, kMatrix = 2 };
+    struct Table { int kind; int64_t len, n1, off; };
+    std::vector<Table> tables;
     int64_t tw_total = 0;
-    auto table_for = [&](int64_t len) -> int64_t {
+    auto table_for = [&](int kind, int64_t len, int64_t n1 = 0) -> int64_t {
         for (auto& t : tables)
-            if (t.first == len) return t.second;
-        tables.push_back({len, tw_total});
-        tw_total += len;
-        return tables.back().second;
+            if (t.kind == kind && t.len == len && t.n1 == n1) return t.off;
+        tables.push_back({kind, len, n1, tw_total});
+        tw_total += kind == kStage ? kTwPlans * len : len;
+        return tables.back().off;
     };
 
     const StorageKind kind = kind_of(dtype);
@@ -501,7 +517,7 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
             Pass P{};
             set_direct(P, g);
             P.axis = g.axis; P.n = g.n; P.four_step = 0;
-            P.tw_off = table_for(g.n); P.tw4_off = -1;
+            P.tw_off = table_for(kStage, g.n); P.tw4_off = -1;
             P.pass_scale = std::ldexp(1.0f, -sp);
             plan->passes.push_back(P);
         } else {
@@ -512,8 +528,9 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
             A.axis = B.axis = g.axis;
             A.n = n1; B.n = n2;
             A.four_step = 1; B.four_step = 2;
-            A.tw_off = table_for(n1); B.tw_off = table_for(n2);
-            A.tw4_off = table_for(g.n); B.tw4_off = -1;
+            A.tw_off = table_for(kStage, n1); B.tw_off = table_for(kStage, n2);
+            A.tw4_off = A.args.tw4_mode == 1 ? table_for(kMatrix, g.n, n1) : table_for(kPlain, g.n);
+            B.tw4_off = -1;
             // the axis scale 2^-sp is split between the two passes
             const int sa = sp / 2, sb = sp - sa;
             A.pass_scale = std::ldexp(1.0f, -sa);
@@ -573,12 +590,26 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     const int mant = tw32 ? 23 : (dtype == WSFFT_C16_FP16 ? 10 : 7);
     const int emin = tw32 ? -126 : (dtype == WSFFT_C16_FP16 ? -14 : -126);
     std::vector<float2> host((size_t)std::max<int64_t>(tw_total, 1));
+    auto put = [&](int64_t at, int64_t m, int64_t len) {
+        double re, im;
+        root_fp64(m, len, &re, &im);
+        host[(size_t)at] = make_float2((float)round_to_format(re, mant, emin), (float)round_to_format(im, mant, emin));
+    };
     for (auto& t : tables) {
-        for (int64_t m = 0; m < t.first; ++m) {
-            double re, im;
-            root_fp64(m, t.first, &re, &im);
-            host[(size_t)(t.second + m)] = make_float2((float)round_to_format(re, mant, emin),
-                                                       (float)round_to_format(im, mant, emin));
+        if (t.kind == kStage) {
+            // entry (r-1)*Ns + k of stage s: W_{Ns*R}^{k*r} = W_len^{k*r*len/(Ns*R)}
+            for (int pl = 0; pl < kTwPlans; ++pl) {
+                const Radices rd = make_radices((int)t.len, pl);
+                const int64_t base = t.off + (int64_t)pl * t.len;
+                for (int st = 1; st < rd.n; ++st) {
+                    const int64_t R = rd.r[st], Ns = stage_ns(rd, st), tws = t.len / (Ns * R);
+                    const int64_t off = stage_tw_offset(rd, st);
+                    for (int64_t r = 1; r < R; ++r)
+                        for (int64_t k = 0; k < Ns; ++k) put(base + off + (r - 1) * Ns + k, k * r * tws, t.len);
+                }
+            }
+        } else {
+            for (int64_t m = 0; m < t.len; ++m) put(t.off + m, t.n1 > 0 ? (m / t.n1) * (m % t.n1) : m, t.len);
         }
     }
     if (hipMalloc(&plan->tw_dev, host.size() * sizeof(float2)) != hipSuccess) {
@@ -596,7 +627,7 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
         return fail(WSFFT_ERROR_OUT_OF_MEMORY);
     }
     for (Pass& P : plan->passes) {
-        P.args.tw = plan->tw_dev + P.tw_off;
+        set_stage_tw(plan, P);
         P.args.tw4 = P.tw4_off >= 0 ? plan->tw_dev + P.tw4_off : nullptr;
         if (P.kern_neg->prepare() != hipSuccess || P.kern_pos->prepare() != hipSuccess) {
             (void)hipFree(plan->tw_dev);
@@ -935,6 +966,7 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
             const Pass& P = p->passes[pi];
             PersistPass q{};
             q.a = P.args;
+            q.a.tw = p->tw_dev + P.tw_off;   // the persistent kernels use radix plan 0
             const bool ip = in[i] == out[i];
             const int ss = ip ? P.src_sel_ip : P.src_sel, ds = ip ? P.dst_sel_ip : P.dst_sel;
             q.a.src = ss == 0 ? in[i] : out[i];
