@@ -187,7 +187,7 @@ def variant_batched(ws, torch, steps, warmup):
             "hbm_frac": byts / (min(ms, ms_persist) * 1e-3) / HBM_PEAK}
 
 
-def variant_rank(ws, torch, shape, steps, warmup, batch=1):
+def variant_rank(ws, torch, shape, steps, warmup, batch=1, one_launch=False):
     import synth
     nx, ny, nz = shape
     N = nx * ny * nz
@@ -201,11 +201,18 @@ def variant_rank(ws, torch, shape, steps, warmup, batch=1):
         ms, _ = time_events(lambda: plan.execute(x, y), steps, warmup)
     else:
         ms, _ = time_events(lambda: ws.execute_many(plan, x, y, batch), steps, warmup)
+    out = {"plan": plan.describe(), "ms": ms, "GFLOPs": batch * flops(N) / (ms * 1e-3) / 1e9,
+           "passes": plan.num_passes,
+           "hbm_frac_min_passes": batch * 2 * 2 * N * 8 / (ms * 1e-3) / HBM_PEAK}
+    if one_launch:
+        # the same transform as a one-entry batch plan: all passes in one launch
+        bp = ws.BatchPlan([plan], [x], [y])
+        out["ms_one_launch"], _ = time_events(bp.execute, steps, warmup)
+        out["one_launch_timed_out"] = bp.timed_out()
+        bp.close()
     del x, y
     torch.cuda.empty_cache()
-    return {"plan": plan.describe(), "ms": ms, "GFLOPs": batch * flops(N) / (ms * 1e-3) / 1e9,
-            "passes": plan.num_passes,
-            "hbm_frac_min_passes": batch * 2 * 2 * N * 8 / (ms * 1e-3) / HBM_PEAK}
+    return out
 
 
 def variant_poisson(ws, torch, steps, warmup):
@@ -316,7 +323,7 @@ def main() -> int:
         variants["batched_96"] = variant_batched(ws, torch, vs, 2)
         variants["2d_8192"] = variant_rank(ws, torch, (8192, 8192, 1), vs, 2)
         variants["1d_65536_x1024"] = variant_rank(ws, torch, (65536, 1, 1), vs, 2, batch=1024)
-        variants["32cubed"] = variant_rank(ws, torch, (32, 32, 32), vs, 2)
+        variants["32cubed"] = variant_rank(ws, torch, (32, 32, 32), vs, 2, one_launch=True)
         variants["poisson_256"] = variant_poisson(ws, torch, vs, 2)
     cpu = None
     if not args.no_cpu_baseline:

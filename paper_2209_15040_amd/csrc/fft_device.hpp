@@ -415,11 +415,14 @@ struct IoF16 {   // FP16 re, FP16 im
     }
 };
 
-// BF16 = top 16 bits of an FP32; storage rounds to nearest even.
-__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // quiet NaN
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+// BF16 = top 16 bits of an FP32; storage rounds to nearest even, both
+// components in one conversion (v_cvt_pk_bf16_f32 on gfx950).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2_rne(float re, float im) {
+    f32x2 v;
+    v.x = re;
+    v.y = im;
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 
 struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
@@ -429,15 +432,14 @@ struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
         return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
     }
     static __device__ __forceinline__ void store(void* p, int64_t i, float2 v) {
-        gstore_ptr<uint32_t>(p)[i] = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
+        gstore_ptr<uint32_t>(p)[i] = f32x2_to_bf16x2_rne(v.x, v.y);
     }
     static __device__ __forceinline__ float2 load_nt(const void* p, int64_t i) {
         const uint32_t w = __builtin_nontemporal_load(gload_ptr<uint32_t>(p) + i);
         return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
     }
     static __device__ __forceinline__ void store_nt(void* p, int64_t i, float2 v) {
-        __builtin_nontemporal_store(f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16),
-                                    gstore_ptr<uint32_t>(p) + i);
+        __builtin_nontemporal_store(f32x2_to_bf16x2_rne(v.x, v.y), gstore_ptr<uint32_t>(p) + i);
     }
     static __device__ __forceinline__ void load2_nt(const void* p, int64_t i, float2& a, float2& b) {
         const uint64_t w = __builtin_nontemporal_load(gload_ptr<uint64_t>(p) + i / 2);
@@ -446,16 +448,13 @@ struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
         b = make_float2(__uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u));
     }
     static __device__ __forceinline__ void store2_nt(void* p, int64_t i, float2 a, float2 b) {
-        const uint64_t w = (uint64_t)(f32_to_bf16_rne(a.x) | (f32_to_bf16_rne(a.y) << 16)) |
-                           ((uint64_t)(f32_to_bf16_rne(b.x) | (f32_to_bf16_rne(b.y) << 16)) << 32);
+        const uint64_t w = (uint64_t)f32x2_to_bf16x2_rne(a.x, a.y) | ((uint64_t)f32x2_to_bf16x2_rne(b.x, b.y) << 32);
         __builtin_nontemporal_store(w, gstore_ptr<uint64_t>(p) + i / 2);
     }
     static __device__ __forceinline__ float2 unpack(uint32_t w) {
         return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
     }
-    static __device__ __forceinline__ uint32_t pack(float2 v) {
-        return f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
-    }
+    static __device__ __forceinline__ uint32_t pack(float2 v) { return f32x2_to_bf16x2_rne(v.x, v.y); }
     template <bool NT> static __device__ __forceinline__ float2 ld(const char* b, uint32_t off) {
         return unpack(NT ? __builtin_nontemporal_load(gload_at<uint32_t>(b, off)) : *gload_at<uint32_t>(b, off));
     }
