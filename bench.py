@@ -210,6 +210,16 @@ def variant_rank(ws, torch, shape, steps, warmup, batch=1, one_launch=False):
         out["ms_one_launch"], _ = time_events(bp.execute, steps, warmup)
         out["one_launch_timed_out"] = bp.timed_out()
         bp.close()
+        # and replayed from a captured HIP graph (the passes as graph nodes)
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            plan.execute(x, y, stream=s)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                plan.execute(x, y, stream=s)
+        out["ms_graph_replay"], _ = time_events(g.replay, steps, warmup)
+        del g
     del x, y
     torch.cuda.empty_cache()
     return out

@@ -50,11 +50,13 @@ constexpr int pow2_floor(int n) {
     return p;
 }
 
-// Elements per thread in the strided layout: 32 for powers of two; radix-3
-// stages leave some threads idle, so fewer there to stay within registers.
+// Elements per thread in the strided layout: 32 for powers of two (16 up to
+// N = 128, so that tiles of these short lengths still have 256 threads and
+// a CU holds 16 waves); radix-3 stages leave some threads idle, so fewer
+// there to stay within registers.
 constexpr int cfg_T_strided(int N, int bytes, int plan = 0) {
     (void)bytes;
-    const int e = is_pow2(N) ? 32 : 24;
+    const int e = is_pow2(N) ? (N <= 128 ? 16 : 32) : 24;
     int t = (N + e - 1) / e;
     const int tmax = N / max_radix(make_radices(N, plan));
     if (tmax >= 1 && t > tmax) t = tmax;
