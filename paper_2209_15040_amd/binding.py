@@ -83,6 +83,7 @@ _batch_destroy = _sig("wsfft_batch_plan_destroy", None, [_vp])
 _real_to_complex = _sig("wsfft_real_to_complex", _int, [_vp, _vp, _i64, _vp])
 _complex_real_part = _sig("wsfft_complex_real_part", _int, [_vp, _vp, _i64, _vp])
 _poisson_symbol = _sig("wsfft_poisson_symbol", _int, [_vp, _i64, _i64, _i64, _vp])
+_poisson_solve = _sig("wsfft_poisson_solve", _int, [_vp, _vp, _vp, _vp, _vp])
 
 
 def _check(st: int, what: str) -> None:
@@ -397,10 +398,49 @@ class PoissonSymbol(torch.autograd.Function):
         return PoissonSymbol.forward(ctx, g)
 
 
-def poisson_solve(f: torch.Tensor) -> torch.Tensor:
-    """u = Re(IFFT(-FFT(f)/|k|^2)) on the periodic box [0, 2*pi)^3, differentiable."""
+def _poisson_fused(f: torch.Tensor):
+    """wsfft_poisson_solve on a (nz, ny, nx) float32 tensor, or None where the
+    grid has no fused kernels."""
+    plan = get_plan(torch.empty(f.shape, dtype=torch.complex64, device=f.device), -1)
+    u = torch.empty_like(f)
+    work = torch.empty(f.shape, dtype=torch.complex64, device=f.device)
+    st = _poisson_solve(plan.handle, f.data_ptr(), u.data_ptr(), work.data_ptr(), _stream(None))
+    if st == 2:   # WSFFT_ERROR_UNSUPPORTED_SIZE
+        return None
+    _check(st, "poisson_solve")
+    return u
+
+
+class PoissonSolve(torch.autograd.Function):
+    """The fused solve; the operator is linear and self-adjoint, so the
+    backward pass is the same solve applied to the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, f):
+        return _poisson_fused(f.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return _poisson_fused(g.contiguous())
+
+
+def poisson_solve(f: torch.Tensor, fused: bool = True) -> torch.Tensor:
+    """u = Re(IFFT(-FFT(f)/|k|^2)) on the periodic box [0, 2*pi)^3, differentiable.
+    Grids with fused kernels run wsfft_poisson_solve (six passes); others, or
+    fused=False, compose the plan's transforms and the elementwise kernels."""
+    if f.dtype != torch.float32 or not f.is_cuda or f.dim() != 3:
+        raise TypeError("poisson_solve takes a (nz, ny, nx) float32 device tensor")
+    if fused and _poisson_fused_supported(tuple(f.shape)):
+        return PoissonSolve.apply(f)
     z = RealToComplex.apply(f)
     F = FFTn.apply(z, -1)
     U = PoissonSymbol.apply(F)
     u = IFFTn.apply(U, -1)
     return ComplexRealPart.apply(u)
+
+
+_FUSED_LENGTHS = (32, 64, 128, 256, 512, 1024)
+
+
+def _poisson_fused_supported(shape) -> bool:
+    return len(shape) == 3 and all(n in _FUSED_LENGTHS for n in shape)

@@ -488,6 +488,11 @@ enum : int {
                             // j*NB .. j*NB+NB-1 of every stage, so its first
                             // loads and last stores come in adjacent pairs that
                             // move as one wider access
+    // Fused Poisson solve (complex64 storage only):
+    kFlagRealIn = 32,       // contiguous layout: the input is real FP32 (imaginary part 0)
+    kFlagPoisson = 64,      // strided layout, z pass of an (nx, ny, N) grid: every stored
+                            // element is multiplied by -1/|k|^2 of its frequency (0 at k = 0)
+    kFlagRealOut = 128,     // strided layout: only the real part is stored, as FP32
 };
 
 // Workgroup id -> tile id such that each XCD gets one contiguous range of
@@ -518,6 +523,8 @@ struct PassArgs {
                           // 2: times W_M^(o1*e), table entry o1*e
     int32_t tstore;       // strided layout only: store columns as contiguous runs via LDS
     float scale;          // multiplies every stored value
+    int32_t sym_nx;       // kFlagPoisson: column c of the z pass is (x, y) = (c mod sym_nx, c div sym_nx)
+    int32_t sym_ny;
 };
 
 // One array of a merged batch launch: the fields of a direct pass that differ
@@ -550,6 +557,13 @@ struct PencilPass {
     static constexpr bool NT = (FLAGS & kFlagNontemporal) != 0;
     static constexpr bool PERSIST = (FLAGS & kFlagPersistent) != 0;
     static constexpr bool FOURSTEP = (FLAGS & kFlagFourStep) != 0;
+    static constexpr bool REALIN = (FLAGS & kFlagRealIn) != 0;
+    static constexpr bool REALOUT = (FLAGS & kFlagRealOut) != 0;
+    static constexpr bool POISSON = (FLAGS & kFlagPoisson) != 0;
+    static_assert(!REALIN || !STRIDED, "real input is read by contiguous passes");
+    static_assert(!(REALOUT || POISSON) || (STRIDED && !FOURSTEP), "fused outputs are strided direct passes");
+    static constexpr int64_t BI = REALIN ? 4 : IO::bytes;    // bytes per input element
+    static constexpr int64_t BO = REALOUT ? 4 : IO::bytes;   // bytes per output element
     __device__ __forceinline__ static float2 gload(const void* p, int64_t i) {
         if constexpr (NT) return IO::load_nt(p, i);
         else return IO::load(p, i);
@@ -557,6 +571,23 @@ struct PencilPass {
     __device__ __forceinline__ static void gstore(void* p, int64_t i, float2 v) {
         if constexpr (NT) IO::store_nt(p, i, v);
         else IO::store(p, i, v);
+    }
+    // first-pass input and last-pass output, real where the fused flags say so
+    __device__ __forceinline__ static float2 gload_in(const void* p, int64_t i) {
+        if constexpr (REALIN) return make_float2(__builtin_nontemporal_load(gload_ptr<float>(p) + i), 0.f);
+        else return gload(p, i);
+    }
+    __device__ __forceinline__ static void gstore_out(void* p, int64_t i, float2 v) {
+        if constexpr (REALOUT) __builtin_nontemporal_store(v.x, gstore_ptr<float>(p) + i);
+        else gstore(p, i, v);
+    }
+    __device__ __forceinline__ static float2 ld_in(const char* b, uint32_t off) {
+        if constexpr (REALIN) return make_float2(__builtin_nontemporal_load(gload_at<float>(b, off)), 0.f);
+        else return IO::template ld<NT>(b, off);
+    }
+    __device__ __forceinline__ static void st_out(char* b, uint32_t off, float2 v) {
+        if constexpr (REALOUT) __builtin_nontemporal_store(v.x, gstore_at<float>(b, off));
+        else IO::template st<NT>(b, off, v);
     }
     static constexpr Radices RD = make_radices(N, PLAN);
     static constexpr int NS = RD.n;
@@ -749,6 +780,30 @@ struct PencilPass {
         return w;
     }
 
+    // Integer wavenumber of index i on an axis of length n: i below ceil(n/2),
+    // i - n from there on (the Nyquist index of an even axis maps to -n/2).
+    __device__ __forceinline__ static float wavenumber(int64_t i, int64_t n) {
+        return (float)(i < (n + 1) / 2 ? i : i - n);
+    }
+    // kx^2 + ky^2 of this thread's column of the z pass (kFlagPoisson).
+    __device__ __forceinline__ static float kxy2_of(const Ctx& c, const PassArgs& a) {
+        const int64_t x = c.col % a.sym_nx, y = c.col / a.sym_nx;
+        const float kx = wavenumber(x, a.sym_nx), ky = wavenumber(y, a.sym_ny);
+        return kx * kx + ky * ky;
+    }
+    // A stored value: the pass scale and, for the Poisson z pass, -1/|k|^2 of
+    // output element e (its kz index), 0 at k = 0.
+    __device__ __forceinline__ static float2 finish(float2 v, int e, float kxy2, const PassArgs& a) {
+        v = cscale(v, a.scale);
+        if constexpr (POISSON) {
+            const float kz = wavenumber(e, N);
+            const float k2 = kxy2 + kz * kz;
+            const float m = k2 > 0.f ? -__builtin_amdgcn_rcpf(k2) : 0.f;
+            v = make_float2(v.x * m, v.y * m);
+        }
+        return v;
+    }
+
     template <int S>
     __device__ __forceinline__ static void store_last(float2* lds, const float2* v, const Ctx& c,
                                                       const PassArgs& a) {
@@ -837,13 +892,15 @@ struct PencilPass {
                     return;
                 }
             }
+            const float kxy2 = POISSON ? kxy2_of(c, a) : 0.f;
 #pragma unroll
             for (int t = 0; t < Q::NB; ++t) {
                 const int b = Q::bf(c.j, t);
                 if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
                 for (int r = 0; r < Q::R; ++r)
-                    IO::template st<NT>(c.ob + (int64_t)eoff<S>(t, r) * c.oes, c.ol, cscale(v[t * Q::R + r], a.scale));
+                    st_out(c.ob + (int64_t)eoff<S>(t, r) * c.oes, c.ol,
+                           finish(v[t * Q::R + r], b + r * Q::NBF, kxy2, a));
             }
             return;
         }
@@ -860,6 +917,7 @@ struct PencilPass {
                 return;
             }
         }
+        const float kxy2 = POISSON ? kxy2_of(c, a) : 0.f;
 #pragma unroll
         for (int t = 0; t < Q::NB; ++t) {
             const int b = Q::bf(c.j, t);
@@ -867,7 +925,7 @@ struct PencilPass {
 #pragma unroll
             for (int r = 0; r < Q::R; ++r) {
                 const int e = b + r * Q::NBF;
-                gstore(a.dst, c.base_out + (int64_t)e * es, cscale(v[t * Q::R + r], a.scale));
+                gstore_out(a.dst, c.base_out + (int64_t)e * es, finish(v[t * Q::R + r], e, kxy2, a));
             }
         }
     }
@@ -894,7 +952,6 @@ struct PencilPass {
     __device__ __forceinline__ static Ctx make_ctx(const PassArgs& a, int64_t t) {
         const int tid = threadIdx.x;
         Ctx c;
-        constexpr int64_t B = IO::bytes;
         if constexpr (STRIDED) {
             const int wave = __builtin_amdgcn_readfirstlane(tid) >> 6;   // wave-uniform
             c.p = tid % P;
@@ -911,13 +968,13 @@ struct PencilPass {
             // the wave's lanes hold rows jw .. jw + JS - 1 (j grows with tid)
             constexpr int JS = (64 + P - 1) / P + 1;
             const int jw = (wave * 64) / P, jl = c.j - jw;
-            c.ies = a.es_in * B;
-            c.oes = a.es_out * B;
-            c.ib = static_cast<const char*>(a.src) + (col0 + c.o1 * a.os1_in + o2 * a.os2_in + jw * a.es_in) * B;
-            c.ob = static_cast<char*>(a.dst) + (col0 * a.cs_out + c.o1 * a.os1_out + o2 * a.os2_out + jw * a.es_out) * B;
-            c.il = (uint32_t)(((c.valid ? c.p : 0) + jl * a.es_in) * B);
-            c.ol = (uint32_t)((c.p * a.cs_out + jl * a.es_out) * B);
-            c.split = (P * B + JS * c.ies) < (int64_t(1) << 32) && (P * a.cs_out * B + JS * c.oes) < (int64_t(1) << 32);
+            c.ies = a.es_in * BI;
+            c.oes = a.es_out * BO;
+            c.ib = static_cast<const char*>(a.src) + (col0 + c.o1 * a.os1_in + o2 * a.os2_in + jw * a.es_in) * BI;
+            c.ob = static_cast<char*>(a.dst) + (col0 * a.cs_out + c.o1 * a.os1_out + o2 * a.os2_out + jw * a.es_out) * BO;
+            c.il = (uint32_t)(((c.valid ? c.p : 0) + jl * a.es_in) * BI);
+            c.ol = (uint32_t)((c.p * a.cs_out + jl * a.es_out) * BO);
+            c.split = (P * BI + JS * c.ies) < (int64_t(1) << 32) && (P * a.cs_out * BO + JS * c.oes) < (int64_t(1) << 32);
         } else {
             c.j = tid % T;
             c.p = tid / T;
@@ -928,13 +985,13 @@ struct PencilPass {
             c.base_out = c.col * a.os1_out;
             // bases at the tile's first pencil
             constexpr int m0 = PAIRS ? St<0>::NB : 1, mL = PAIRS ? St<NS - 1>::NB : 1;
-            c.ies = B;
-            c.oes = B;
-            c.ib = static_cast<const char*>(a.src) + t * P * a.os1_in * B;
-            c.ob = static_cast<char*>(a.dst) + t * P * a.os1_out * B;
-            c.il = (uint32_t)(((c.valid ? c.p : 0) * a.os1_in + c.j * m0) * B);
-            c.ol = (uint32_t)((c.p * a.os1_out + c.j * mL) * B);
-            c.split = (P * a.os1_in + N) * B < (int64_t(1) << 32) && (P * a.os1_out + N) * B < (int64_t(1) << 32);
+            c.ies = BI;
+            c.oes = BO;
+            c.ib = static_cast<const char*>(a.src) + t * P * a.os1_in * BI;
+            c.ob = static_cast<char*>(a.dst) + t * P * a.os1_out * BO;
+            c.il = (uint32_t)(((c.valid ? c.p : 0) * a.os1_in + c.j * m0) * BI);
+            c.ol = (uint32_t)((c.p * a.os1_out + c.j * mL) * BO);
+            c.split = (P * a.os1_in + N) * BI < (int64_t(1) << 32) && (P * a.os1_out + N) * BO < (int64_t(1) << 32);
         }
         return c;
     }
@@ -945,7 +1002,7 @@ struct PencilPass {
     // pairs (decided on the unpaired instance: the butterfly counts are the
     // same under both mappings).
     static constexpr bool pairs_help() {
-        return !STRIDED && NT && St<0>::FULL && St<0>::NB % 2 == 0 && St<0>::NBF % 2 == 0;
+        return !STRIDED && NT && !REALIN && St<0>::FULL && St<0>::NB % 2 == 0 && St<0>::NBF % 2 == 0;
     }
 
     // First-stage inputs straight from HBM.
@@ -982,8 +1039,7 @@ struct PencilPass {
                 const int b = Q::bf(c.j, t);
                 if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
-                for (int r = 0; r < Q::R; ++r)
-                    v[t * Q::R + r] = IO::template ld<NT>(c.ib + (int64_t)eoff<0>(t, r) * c.ies, c.il);
+                for (int r = 0; r < Q::R; ++r) v[t * Q::R + r] = ld_in(c.ib + (int64_t)eoff<0>(t, r) * c.ies, c.il);
             }
             return;
         }
@@ -1006,7 +1062,7 @@ struct PencilPass {
             if (!Q::FULL && b >= Q::NBF) continue;
 #pragma unroll
             for (int r = 0; r < Q::R; ++r)
-                v[t * Q::R + r] = c.valid ? gload(a.src, c.base_in + (int64_t)(b + r * Q::NBF) * es)
+                v[t * Q::R + r] = c.valid ? gload_in(a.src, c.base_in + (int64_t)(b + r * Q::NBF) * es)
                                           : make_float2(0.f, 0.f);
         }
     }

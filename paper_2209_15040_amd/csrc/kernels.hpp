@@ -20,7 +20,11 @@ struct PassKernel {
     // batch of direct passes (PassArgs supplies the shared fields)
     hipError_t (*launch)(const PassArgs&, const BatchTable* bt, dim3 grid, hipStream_t);
     hipError_t (*prepare)();   // one-time function attributes
+    int fused;          // 0: plain pass; Poisson solve passes (complex64 only):
+                        // 1 real input, 2 times -1/|k|^2, 3 real output
 };
+
+enum FusedKind { kFusedNone = 0, kFusedRealIn = 1, kFusedPoisson = 2, kFusedRealOut = 3 };
 
 // NULL when no kernel of that length/layout/variant exists.
 const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided, bool four_step,
@@ -35,5 +39,9 @@ WSFFT_DECLARE_FIND(find_pass_f16_pos)
 WSFFT_DECLARE_FIND(find_pass_bf16_neg)
 WSFFT_DECLARE_FIND(find_pass_bf16_pos)
 #undef WSFFT_DECLARE_FIND
+// Fused Poisson-solve kernels (complex64; real input and the multiplier with
+// sign -1, real output with sign +1).  NULL when none exists for n.
+const PassKernel* find_fused_c64_neg(int n, bool strided, int fused);
+const PassKernel* find_fused_c64_pos(int n, bool strided, int fused);
 
 }  // namespace wsfft

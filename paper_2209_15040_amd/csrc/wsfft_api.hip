@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "../../include/wsfft.h"
+#include "../../include/wsfft_pointwise.h"
 #include "kernels.hpp"
 #include "pass_config.hpp"
 #include "persist.hpp"
@@ -835,6 +836,50 @@ wsfft_status_t wsfft_execute_adjoint(wsfft_plan_t plan, const void* in, void* ou
 wsfft_status_t wsfft_execute_inverse(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream) {
     const wsfft_status_t st = check_exec(plan, in, out);
     return st != WSFFT_SUCCESS ? st : exec_plan(plan, in, out, 2, stream);
+}
+
+wsfft_status_t wsfft_poisson_solve(wsfft_plan_t plan, const float* f, float* u, void* work, hipStream_t stream) {
+    using namespace wsfft;
+    if (!plan_live(plan)) return WSFFT_ERROR_INVALID_PLAN;
+    if (!f || !u || !work) return WSFFT_ERROR_NULL_POINTER;
+    if (((uintptr_t)f % 4) || ((uintptr_t)u % 4) || ((uintptr_t)work % 8)) return WSFFT_ERROR_MISALIGNED;
+    if (work == (const void*)f || work == (void*)u) return WSFFT_ERROR_INVALID_VALUE;
+    if (plan->dtype != WSFFT_C64) return WSFFT_ERROR_UNSUPPORTED_SIZE;
+    // three direct passes x (contiguous), y, z (strided), each with fused kernels
+    const auto& ps = plan->passes;
+    if (ps.size() != 3) return WSFFT_ERROR_UNSUPPORTED_SIZE;
+    for (int i = 0; i < 3; ++i)
+        if (ps[i].four_step != 0 || ps[i].axis != i || ps[i].strided != (i > 0)) return WSFFT_ERROR_UNSUPPORTED_SIZE;
+    const int64_t nx = plan->n[0], ny = plan->n[1], nz = plan->n[2];
+    const PassKernel* kin = find_fused_c64_neg((int)nx, false, kFusedRealIn);
+    const PassKernel* ksym = find_fused_c64_neg((int)nz, true, kFusedPoisson);
+    const PassKernel* kout = find_fused_c64_pos((int)nz, true, kFusedRealOut);
+    if (!kin || !ksym || !kout || nx > INT32_MAX || ny > INT32_MAX) return WSFFT_ERROR_UNSUPPORTED_SIZE;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
+    if (cur != plan->device) return WSFFT_ERROR_WRONG_DEVICE;
+    if (kin->prepare() != hipSuccess || ksym->prepare() != hipSuccess || kout->prepare() != hipSuccess)
+        return WSFFT_ERROR_HIP;
+    auto go = [&](const Pass& P, const PassKernel* k, const void* src, void* dst, float scale) {
+        PassArgs a = P.args;
+        a.src = src;
+        a.dst = dst;
+        a.scale = scale;
+        a.tw = plan->tw_dev + P.tw_off + (int64_t)k->plan * P.n;   // the stage tables of k's radix plan
+        a.sym_nx = (int32_t)nx;
+        a.sym_ny = (int32_t)ny;
+        return k->launch(a, nullptr, dim3((unsigned)blocks_for(P, k)), stream) == hipSuccess;
+    };
+    const double N = (double)nx * (double)ny * (double)nz;
+    const bool ok =
+        // forward, sign -1: real input, then y, then z times -1/|k|^2
+        go(ps[0], kin, f, work, ps[0].pass_scale) && go(ps[1], ps[1].kern_neg, work, work, ps[1].pass_scale) &&
+        go(ps[2], ksym, work, work, ps[2].pass_scale) &&
+        // inverse, sign +1: x, y, then z storing the real part times 1/N
+        go(ps[0], ps[0].kern_pos, work, work, ps[0].pass_scale) &&
+        go(ps[1], ps[1].kern_pos, work, work, ps[1].pass_scale) &&
+        go(ps[2], kout, work, u, (float)((double)ps[2].pass_scale / N));
+    return ok ? WSFFT_SUCCESS : WSFFT_ERROR_HIP;
 }
 
 wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const void* in, void* out,

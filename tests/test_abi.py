@@ -128,6 +128,14 @@ def test_pointwise_argument_checks(lib):
     assert lib.wsfft_poisson_symbol(0x1004, 4, 4, 4, None) == MISALIGNED
 
 
+def test_poisson_solve_argument_checks(lib):
+    f = lib.wsfft_poisson_solve
+    f.argtypes = [ctypes.c_void_p] * 5
+    bogus = ctypes.c_void_p(0x1000)
+    assert f(None, 0x1000, 0x2000, 0x3000, None) == BADPLAN
+    assert f(bogus, 0x1000, 0x2000, 0x3000, None) == BADPLAN
+
+
 def test_status_strings(lib):
     for s in range(10):
         assert lib.wsfft_status_string(s)

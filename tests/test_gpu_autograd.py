@@ -139,3 +139,46 @@ def test_poisson_per_coordinate_fd_small(ws):
         lm = float(np.sum(to_host(ws.poisson_solve(ft - e)).astype(np.float64) * w.astype(np.float32)))
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[idx]) <= 2e-3 * max(1.0, abs(g[idx]))
+
+
+# --- the fused solve (wsfft_poisson_solve: six passes, no elementwise passes) --------
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (32, 64, 128), (256, 32, 64)], ids=lambda s: "x".join(map(str, s)))
+def test_poisson_fused_matches_fp64_operator(ws, shape):
+    nz, ny, nx = shape
+    f = synth.normal_c(shape, seed=21).real
+    ft = torch.from_numpy(f.astype(np.float32)).cuda()
+    u = ws.poisson_solve(ft)                       # fused: every axis has a fused kernel
+    u_ref = oracle.poisson_apply(f.astype(np.float32).astype(np.float64))
+    e = rel_l2(to_host(u), u_ref)
+    print(f"fused poisson {shape}: rel_l2 {e:.3e}")
+    assert e <= 1e-5
+    u_c = ws.poisson_solve(ft, fused=False)        # composed from the plan and the pointwise kernels
+    assert rel_l2(to_host(u), to_host(u_c)) <= 1e-5
+
+
+def test_poisson_fused_gradient_and_in_place(ws):
+    n = 64
+    f, w = _poisson_inputs(n, 22)
+    fg = torch.from_numpy(f.astype(np.float32)).cuda().requires_grad_(True)
+    wt = torch.from_numpy(w.astype(np.float32)).cuda()
+    (ws.poisson_solve(fg) * wt).sum().backward()
+    g_ref = oracle.poisson_loss_grad(w.astype(np.float32).astype(np.float64))
+    assert rel_l2(to_host(fg.grad), g_ref) <= 1e-5
+    # f and u may be the same array
+    x = torch.from_numpy(f.astype(np.float32)).cuda()
+    plan = ws.get_plan(torch.empty(x.shape, dtype=torch.complex64, device="cuda"), -1)
+    work = torch.empty(x.shape, dtype=torch.complex64, device="cuda")
+    assert ws._poisson_solve(plan.handle, x.data_ptr(), x.data_ptr(), work.data_ptr(), ws._stream(None)) == 0
+    assert rel_l2(to_host(x), oracle.poisson_apply(f.astype(np.float32).astype(np.float64))) <= 1e-5
+
+
+def test_poisson_unsupported_grid_composes(ws):
+    shape = (32, 48, 96)                  # 96 and 48 have no fused kernels
+    f = synth.normal_c(shape, seed=23).real.astype(np.float32)
+    ft = torch.from_numpy(f).cuda()
+    plan = ws.get_plan(torch.empty(shape, dtype=torch.complex64, device="cuda"), -1)
+    work = torch.empty(shape, dtype=torch.complex64, device="cuda")
+    u = torch.empty_like(ft)
+    assert ws._poisson_solve(plan.handle, ft.data_ptr(), u.data_ptr(), work.data_ptr(), ws._stream(None)) == 2
+    assert rel_l2(to_host(ws.poisson_solve(ft)), oracle.poisson_apply(f.astype(np.float64))) <= 1e-5
