@@ -185,3 +185,21 @@ def test_1d_batch_65536(ws):
     e = rel_l2(yh[sel], ref)
     print(f"1D 1024x65536 rel_l2 {e:.3e} (every 64th pencil)")
     assert e <= TOL
+
+
+# --- limits of the axis lengths ---------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(1 << 20, 1, 1), (3 ** 12, 1, 1), (2, 6561, 3)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_longest_axes(ws, shape):
+    """The longest axis a plan accepts (2^20, split 1024 x 1024), the longest
+    pure radix-3 axis below it (3^12, split 729 x 729) and a long radix-3
+    strided axis (6561 = 81 x 81)."""
+    nx, ny, nz = shape
+    a = synth.normal_c((nz, ny, nx), seed=12).astype(np.complex64)
+    y, p = run_plan(ws, a, -1)
+    e = rel_l2(y, oracle.fftn(a.astype(np.complex128), -1))
+    print(f"{shape}: rel_l2 {e:.3e} [{p.describe()}]")
+    assert e <= TOL
+    y2, _ = run_plan(ws, a, -1, "execute_inverse")
+    assert rel_l2(y2, oracle.fftn(a.astype(np.complex128), +1) / a.size) <= TOL

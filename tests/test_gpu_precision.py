@@ -88,3 +88,35 @@ def test_constant_input_stays_finite(ws):
     y = c16_to_c128(p.execute(c16_to_dev(pairs, "fp16")), "fp16")
     assert np.isfinite(y).all()
     assert abs(y[0, 0, 0] * 2.0 ** p.scale_log2 - n ** 3) <= 1e-3 * n ** 3
+
+
+@pytest.mark.parametrize("kind", ["fp16", "bf16"])
+@pytest.mark.parametrize("shape", [(64, 32, 16), (96, 27, 8), (8192, 1, 4)], ids=lambda s: "x".join(map(str, s)))
+def test_adjoint_and_inverse_16bit(ws, kind, shape):
+    """The adjoint (opposite sign) and the inverse (adjoint times 1/N) with
+    16-bit storage, against the oracle on the same rounded input; stored
+    results are 2^-S times the exact ones."""
+    nx, ny, nz = shape
+    z = synth.normal_c((nz, ny, nx), seed=13, scale=0.5)
+    pairs = round_pairs(z, kind)
+    a = synth.pairs_to_c128(pairs, kind)
+    p = ws.Plan(nx, ny, nz, kind, -1)
+    bound = (3e-3 if kind == "fp16" else 6e-3) * max(1.0, (p.num_passes / 3) ** 0.5)
+    x = c16_to_dev(pairs, kind)
+    adj = c16_to_c128(p.execute_adjoint(x), kind) * 2.0 ** p.scale_log2
+    assert rel_l2(adj, oracle.fftn(a, +1)) <= bound
+    inv = c16_to_c128(p.execute_inverse(x), kind) * 2.0 ** p.scale_log2
+    assert rel_l2(inv, oracle.fftn(a, +1) / a.size) <= bound
+
+
+def test_batched_16bit_matches_single_calls(ws):
+    shapes = [(32, 64, 16), (64, 32, 32), (128, 16, 8)]
+    plans = [ws.Plan(*s, "fp16", -1) for s in shapes]
+    xs = [c16_to_dev(synth.to_fp16_pairs(synth.normal_c((s[2], s[1], s[0]), seed=50 + i, scale=0.5)), "fp16")
+          for i, s in enumerate(shapes)]
+    ys = [torch.empty_like(x) for x in xs]
+    ws.execute_batched(plans, xs, ys)
+    for p, x, y in zip(plans, xs, ys):
+        single = p.execute(x)
+        torch.cuda.synchronize()
+        assert torch.equal(single, y)
