@@ -12,8 +12,9 @@
 // * 32 elements per thread, the exchange split into rounds of up to ~72 KB
 //   of LDS, so two workgroups stay resident per CU and one's transform and
 //   store drain overlap the other's loads;
-// * contiguous pencils: 16 elements per thread, 256-thread workgroups, and
-//   paired (two-element) first-stage loads where the stage allows them;
+// * contiguous pencils: 16 elements per thread, 256-thread workgroups
+//   (64 for the 4-byte types), and paired (two-element) first-stage loads
+//   where the stage allows them;
 // * non-temporal (streaming) loads and stores help every pass.
 #pragma once
 #include "fft_device.hpp"
@@ -38,8 +39,11 @@ constexpr int cfg_T_contig(int N, int plan = 0) {
     if (tmax >= 1 && t > tmax) t = tmax;
     return t > 1024 ? 1024 : t;
 }
-constexpr int cfg_P_contig(int N, int plan = 0) {
-    const int p = 256 / cfg_T_contig(N, plan);
+// Contiguous tiles: 256-thread workgroups for complex64; one wave for the
+// 4-byte types, whose tiles carry half the bytes, so more workgroups (and
+// more bytes in flight) fit per CU within the same FP32 LDS budget.
+constexpr int cfg_P_contig(int N, int plan = 0, int bytes = 8) {
+    const int p = (bytes == 8 ? 256 : 64) / cfg_T_contig(N, plan);
     return p < 1 ? 1 : p;
 }
 
