@@ -58,9 +58,12 @@ constexpr int pow2_floor(int n) {
 // N = 128, so that tiles of these short lengths still have 256 threads and
 // a CU holds 16 waves); radix-3 stages leave some threads idle, so fewer
 // there to stay within registers.
+// Past 512 threads per tile (32 columns x 16 threads) the elements per thread
+// double instead: 1024-thread workgroups are held to 128 VGPRs and spill.
 constexpr int cfg_T_strided(int N, int bytes, int plan = 0) {
     (void)bytes;
-    const int e = is_pow2(N) ? (N <= 128 ? 16 : 32) : 24;
+    int e = is_pow2(N) ? (N <= 128 ? 16 : 32) : 24;
+    if ((N + e - 1) / e > 16) e *= 2;
     int t = (N + e - 1) / e;
     const int tmax = N / max_radix(make_radices(N, plan));
     if (tmax >= 1 && t > tmax) t = tmax;
@@ -75,11 +78,13 @@ constexpr int cfg_P_strided(int N, int bytes, int plan = 0) {
 }
 // Smallest K dividing N whose exchange round fits the LDS budget (twice the
 // per-round budget for workgroups of up to 512 threads, two of which still
-// fit per CU); when that takes more than 8 rounds, accept up to twice the
-// budget instead.
+// fit per CU; four times at 1024 points); when that takes more than 8
+// rounds, accept up to twice the budget instead.
 constexpr int cfg_K_strided(int N, int bytes, int plan = 0) {
     const int p = cfg_P_strided(N, bytes, plan);
-    const int budget = cfg_T_strided(N, bytes, plan) * p <= 512 ? 2 * kLdsRoundBudget : kLdsRoundBudget;
+    // 1024-point tiles run best with two rounds and one workgroup per CU
+    const int budget = N >= 1024 ? 4 * kLdsRoundBudget
+                       : cfg_T_strided(N, bytes, plan) * p <= 512 ? 2 * kLdsRoundBudget : kLdsRoundBudget;
     int first = 0;
     for (int k = 1; k <= N && !first; ++k)
         if (N % k == 0 && (N / k) * (p + 1) * 8 <= budget) first = k;
