@@ -773,8 +773,8 @@ struct PencilPass {
     // consecutive entries; mode 2 (g = o1, the same for the whole tile) reads
     // the plain table W_M^m at m = g*e.
     __device__ __forceinline__ static float2 tw4_of(int e, int64_t col, int64_t o1, const PassArgs& a) {
-        const int64_t m = a.tw4_mode == 1 ? col * N + e : o1 * e;
-        const f32x2 wv = gload_ptr<f32x2>(a.tw4)[m];
+        const uint32_t m = a.tw4_mode == 1 ? (uint32_t)col * N + e : (uint32_t)o1 * e;   // < M <= 2^20
+        const f32x2 wv = *gload_at<f32x2>(reinterpret_cast<const char*>(a.tw4), m * 8u);
         float2 w = make_float2(wv.x, wv.y);
         if (SIGN > 0) w.y = -w.y;
         return w;
@@ -813,6 +813,15 @@ struct PencilPass {
             // and each column leaves as contiguous runs of ROWS elements.
             const int64_t c0 = c.col - c.p;
             const int64_t b0 = c.base_out - c.p * a.cs_out;
+            // tile-uniform bases with 32-bit per-lane byte offsets: the store
+            // offset pl*cs_out + e*es_out (when it fits) and the twiddle entry,
+            // (c0 + pl)*N + e (mode 1) or o1*e (mode 2), both below M
+            constexpr int64_t B = IO::bytes;
+            char* const obase = static_cast<char*>(a.dst) + b0 * B;
+            const bool fit = (P * a.cs_out + N * a.es_out) * B < (int64_t(1) << 32);
+            const uint32_t cs32 = (uint32_t)(a.cs_out * B), es32 = (uint32_t)(a.es_out * B);
+            const char* const twbase = reinterpret_cast<const char*>(a.tw4) + (a.tw4_mode == 1 ? c0 * N * 8 : 0);
+            const uint32_t o1w = (uint32_t)c.o1;
 #pragma unroll
             for (int h = 0; h < K; ++h) {
                 __syncthreads();
@@ -835,8 +844,14 @@ struct PencilPass {
                     for (int i = 0; i < PER; ++i) {
                         const int idx = threadIdx.x + i * T * P;
                         const int pl = idx / ROWS, el = idx % ROWS;
-                        w4[i] = (idx < ROWS * P && c0 + pl < a.C) ? tw4_of(el + h * ROWS, c0 + pl, c.o1, a)
-                                                                  : make_float2(1.f, 0.f);
+                        const uint32_t e = (uint32_t)(el + h * ROWS);
+                        const uint32_t m = a.tw4_mode == 1 ? (uint32_t)pl * N + e : o1w * e;
+                        if (idx < ROWS * P && c0 + pl < a.C) {
+                            const f32x2 wv = *gload_at<f32x2>(twbase, m * 8u);
+                            w4[i] = make_float2(wv.x, SIGN > 0 ? -wv.y : wv.y);
+                        } else {
+                            w4[i] = make_float2(1.f, 0.f);
+                        }
                     }
                 }
                 __syncthreads();
@@ -849,7 +864,8 @@ struct PencilPass {
                     if (col >= a.C) continue;
                     float2 x = lds[lidx(pl, el)];
                     if (FOURSTEP && a.tw4_mode != 0) x = cmul(x, w4[i]);
-                    gstore(a.dst, b0 + pl * a.cs_out + (int64_t)e * a.es_out, cscale(x, a.scale));
+                    if (fit) IO::template st<NT>(obase, (uint32_t)pl * cs32 + (uint32_t)e * es32, cscale(x, a.scale));
+                    else gstore(a.dst, b0 + pl * a.cs_out + (int64_t)e * a.es_out, cscale(x, a.scale));
                 }
             }
             return;
