@@ -547,12 +547,12 @@ struct BatchTable {
 
 // ------------------------------------------------------------ the kernel ---
 // N: pencil length.  T: threads per pencil.  P: pencils (contiguous layout)
-// or columns (strided layout) per workgroup.  K: the strided layout's LDS
-// exchanges run in K rounds over N/K rows each, so a wide tile needs only
+// or columns (strided layout) per workgroup.  K: the LDS
+// exchanges run in K rounds over N/K elements of each pencil (rows of a
+// strided tile), so a wide tile or a long pencil needs only
 // 1/K of its size in LDS and more workgroups stay resident per CU.
 template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1, int PLAN = 0>
 struct PencilPass {
-    static_assert(STRIDED || K == 1, "split exchanges are for the strided layout");
     static_assert(N % K == 0, "K must divide N");
     static constexpr bool NT = (FLAGS & kFlagNontemporal) != 0;
     static constexpr bool PERSIST = (FLAGS & kFlagPersistent) != 0;
@@ -605,7 +605,7 @@ struct PencilPass {
         return sh < 3 ? 3 : (sh > 6 ? 6 : sh);
     }
     static constexpr int PADSH = pad_shift();
-    static constexpr int LDS_ROW = STRIDED ? (P + 1) : (N + (N >> PADSH) + 1);
+    static constexpr int LDS_ROW = STRIDED ? (P + 1) : (ROWS + (ROWS >> PADSH) + 1);
     static constexpr int LDS_ELEMS = STRIDED ? ROWS * (P + 1) : P * LDS_ROW;
     static constexpr int lds_bytes() { return (LDS_ELEMS + (PERSIST ? N : 0)) * 8; }
     static constexpr int threads() { return T * P; }
