@@ -25,15 +25,23 @@ constexpr int kLdsBytesMax = 160 * 1024;   // LDS per CU on gfx950
 constexpr int kLdsRoundBudget = 36 * 1024; // LDS per exchange round, 256-thread strided tiles
 constexpr int kPassFlags = kFlagNontemporal;
 
+// Radix plan of the default contiguous kernel: the fewest stages, except
+// that pencils of up to 32 points take radix <= 8 stages so that 4 threads
+// share a pencil (cfg_T_contig).
+constexpr int cfg_plan_contig(int N) { return N <= 32 ? 2 : 0; }
+
 // Radix plan of the default strided kernel (see make_radices).
 constexpr int cfg_plan_strided(int N, int bytes) {
     (void)N;
     return bytes == 8 ? 1 : 0;
 }
 
+// At least 4 threads per pencil where the radix plan allows: with one
+// thread per pencil a wave's 64 lanes read 64 pencils, 64 cache lines per
+// access.
 constexpr int cfg_T_contig(int N, int plan = 0) {
     int t = N / 16;
-    if (t < 1) t = 1;
+    if (t < 4) t = 4;
     // every thread must own at least one butterfly of the widest stage
     const int tmax = N / max_radix(make_radices(N, plan));
     if (tmax >= 1 && t > tmax) t = tmax;

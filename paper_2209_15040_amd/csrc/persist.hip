@@ -29,9 +29,11 @@ constexpr int kPT = kPersistThreads;
 constexpr int kPersistFlags = kPassFlags;
 
 // Geometry in the persistent kernel: one butterfly of the widest radix per
-// thread and exactly kPersistThreads threads per workgroup.
+// thread and exactly kPersistThreads threads per workgroup.  Contiguous
+// 32-point pencils take radix <= 8 stages, 4 threads per pencil: with one
+// thread per pencil a wave's loads touch 64 cache lines each.
 template <int N, bool ST> struct PGeo {
-    static constexpr int PLAN = 0;
+    static constexpr int PLAN = (!ST && N == 32) ? 2 : 0;
     static constexpr int T = N / max_radix(make_radices(N, PLAN));
     static constexpr int P = kPT / T;
     static_assert(T * P == kPT, "persistent geometry must fill the workgroup");
@@ -84,7 +86,7 @@ __device__ __forceinline__ unsigned load_acquire(const unsigned* p) {
 // the other lanes keep cycling through the barriers.  The iteration cap
 // bounds the loop whatever shape it is compiled to.
 template <int SIGN>
-__global__ __launch_bounds__(kPT, 2) void persist_kernel(const PersistPass* __restrict__ passes, int npasses,
+__global__ __launch_bounds__(kPT, 3) void persist_kernel(const PersistPass* __restrict__ passes, int npasses,
                                                       PersistLevels lv, PersistCounters* ctr, unsigned spin_limit) {
     extern __shared__ float2 lds_dyn[];
     __shared__ int64_t s_item;
@@ -187,6 +189,14 @@ int persist_per_block(int n, bool strided) {
     if (n == N && strided == ST) return PGeo<N, ST>::P;
     WSFFT_PERSIST_TYPES(WSFFT_PER)
 #undef WSFFT_PER
+    return 0;
+}
+
+int persist_plan(int n, bool strided) {
+#define WSFFT_PLAN(I, N, ST) \
+    if (n == N && strided == ST) return PGeo<N, ST>::PLAN;
+    WSFFT_PERSIST_TYPES(WSFFT_PLAN)
+#undef WSFFT_PLAN
     return 0;
 }
 

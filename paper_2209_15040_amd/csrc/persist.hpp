@@ -36,6 +36,7 @@ struct PersistCounters {
 
 int persist_type(int n, bool strided);        // -1: no persistent kernel for it
 int persist_per_block(int n, bool strided);   // pencils or columns per workgroup
+int persist_plan(int n, bool strided);        // radix plan of that branch (its stage twiddle table)
 int persist_lds_bytes();
 hipError_t persist_prepare(int* blocks_per_cu);
 hipError_t persist_launch(int sign, const PersistPass* passes, int npasses, const PersistLevels& levels,

@@ -1011,7 +1011,8 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
             const Pass& P = p->passes[pi];
             PersistPass q{};
             q.a = P.args;
-            q.a.tw = p->tw_dev + P.tw_off;   // the persistent kernels use radix plan 0
+            // the stage twiddles of the persistent branch's radix plan
+            q.a.tw = p->tw_dev + P.tw_off + (int64_t)persist_plan((int)P.n, P.strided) * P.n;
             const bool ip = in[i] == out[i];
             const int ss = ip ? P.src_sel_ip : P.src_sel, ds = ip ? P.dst_sel_ip : P.dst_sel;
             q.a.src = ss == 0 ? in[i] : out[i];
