@@ -1090,6 +1090,15 @@ struct PencilPass {
         load_first(v, c, a);
         stages<0>(lds, v, c, a, a.tw);
     }
+    // The same, calling after_loads() once the tile's loads are issued.
+    template <class H>
+    __device__ __forceinline__ static void run_tile(const PassArgs& a, int64_t t, float2* lds, H&& after_loads) {
+        const Ctx c = make_ctx(a, t);
+        float2 v[maxv()];
+        load_first(v, c, a);
+        after_loads();
+        stages<0>(lds, v, c, a, a.tw);
+    }
 
     __device__ __forceinline__ static void run(const PassArgs& a0, const BatchTable& bt, float2* lds) {
         if constexpr (!PERSIST) {

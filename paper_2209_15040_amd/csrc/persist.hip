@@ -63,11 +63,11 @@ constexpr int lds_max() {
 }
 constexpr int kPersistLds = lds_max();
 
-template <int SIGN>
-__device__ __forceinline__ void run_type(int type, const PassArgs& a, int64_t t, float2* lds) {
+template <int SIGN, class H>
+__device__ __forceinline__ void run_type(int type, const PassArgs& a, int64_t t, float2* lds, H&& after_loads) {
     switch (type) {
 #define WSFFT_CASE(I, N, ST) \
-    case I: PGeo<N, ST>::template PP<SIGN>::run_tile(a, t, lds); break;
+    case I: PGeo<N, ST>::template PP<SIGN>::run_tile(a, t, lds, after_loads); break;
         WSFFT_PERSIST_TYPES(WSFFT_CASE)
 #undef WSFFT_CASE
         default: break;
@@ -91,35 +91,31 @@ __global__ __launch_bounds__(kPT, 3) void persist_kernel(const PersistPass* __re
     extern __shared__ float2 lds_dyn[];
     __shared__ int64_t s_item;
     __shared__ int s_pass;
+    __shared__ unsigned s_next;   // the ticket claimed during the previous tile
     const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;   // wave-uniform
     const bool lane0 = threadIdx.x == 0;
     const int64_t total = lv.end[lv.count - 1];
     int level = -1;          // level of the tiles finished since the last publication
     unsigned pending = 0;    // those tiles
-    unsigned next = 0;       // lane 0 of wave 0: the ticket claimed ahead
-    bool have_next = false;
+    bool first = true;
     int cur = 0;             // wave 0: pass of the last item (items only grow)
     for (int64_t iter = 0; iter <= total; ++iter) {
         if (wave0) {
             unsigned got = 0;
-            if (lane0) got = have_next ? next : atomicAdd(&ctr->ticket, 1u);
+            if (lane0) got = first ? atomicAdd(&ctr->ticket, 1u) : s_next;
             const int64_t item = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)got);
             int pi = -1;
             if (item < total) {
                 // the pass holding this item (passes sorted by `first`)
                 while (cur + 1 < npasses && passes[cur + 1].first <= item) ++cur;
                 pi = cur;
-                // claim the following ticket now; its latency hides behind this tile.
-                // A held ticket is never of a lower level than the current one,
-                // so waiting for the previous level cannot depend on it.
-                if (lane0) next = atomicAdd(&ctr->ticket, 1u);
             }
-            have_next = true;
             if (lane0) {
                 s_item = item;
                 s_pass = pi;
             }
         }
+        first = false;
         __syncthreads();
         const int pi = __builtin_amdgcn_readfirstlane(s_pass);
         const int L = pi < 0 ? kPersistMaxLevels : __builtin_amdgcn_readfirstlane(passes[pi].level);
@@ -158,7 +154,16 @@ __global__ __launch_bounds__(kPT, 3) void persist_kernel(const PersistPass* __re
         const int64_t item = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(iv >> 32)) << 32) |
                                        (uint32_t)__builtin_amdgcn_readfirstlane((int)iv));
         const PersistPass& P = passes[pi];
-        run_type<SIGN>(P.type, P.a, item - P.first, lds_dyn);
+        // Claim the following ticket before this tile's loads and read it back
+        // right after them: the wait for it is then not a wait for this or the
+        // previous tile's stores (loads and stores share one in-order
+        // counter).  A held ticket is never of a lower level than the current
+        // one, so waiting for the previous level cannot depend on it.
+        unsigned nxt = 0;
+        if (lane0) nxt = atomicAdd(&ctr->ticket, 1u);
+        run_type<SIGN>(P.type, P.a, item - P.first, lds_dyn, [&] {
+            if (lane0) s_next = nxt;
+        });
         __syncthreads();   // LDS and the shared slots free for the next tile
         ++pending;
     }
