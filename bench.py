@@ -40,6 +40,7 @@ MEASURED_TRAFFIC = {     # source hash -> counters of the dominant (z) pass kern
                          "profile": "profiles/pencil_pass_512cubed_c64_hbm_counters.md"},
 }
 
+
 def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
