@@ -475,12 +475,6 @@ struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
 // Kernel feature flags (template parameter FLAGS).
 enum : int {
     kFlagNontemporal = 1,   // streaming (non-temporal) global loads and stores
-    kFlagXcdOrder = 2,      // consecutive tiles on one XCD (the hardware deals
-                            // workgroups round-robin over the 8 XCDs)
-    kFlagPersistent = 4,    // one resident grid walks all tiles; the next tile's
-                            // inputs load while the current one is transformed,
-                            // and the twiddle table sits in LDS so no global
-                            // load waits behind that prefetch
     kFlagFourStep = 8,      // first pass of a split axis: inter-pass twiddles
                             // and the transposed store (PassArgs tw4_mode,
                             // tstore) are compiled in only with this flag
@@ -494,13 +488,6 @@ enum : int {
                             // element is multiplied by -1/|k|^2 of its frequency (0 at k = 0)
     kFlagRealOut = 128,     // strided layout: only the real part is stored, as FP32
 };
-
-// Workgroup id -> tile id such that each XCD gets one contiguous range of
-// tiles: XCD x = b mod 8 runs tiles [x*q + min(x, r), ...) in order.
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
-    const int64_t q = G / 8, r = G % 8, x = b % 8, i = b / 8;
-    return x * q + (x < r ? x : r) + i;
-}
 
 // -------------------------------------------------------------- pass args ---
 // A pass transforms pencils of length N.  Two layouts:
@@ -555,7 +542,6 @@ template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, 
 struct PencilPass {
     static_assert(N % K == 0, "K must divide N");
     static constexpr bool NT = (FLAGS & kFlagNontemporal) != 0;
-    static constexpr bool PERSIST = (FLAGS & kFlagPersistent) != 0;
     static constexpr bool FOURSTEP = (FLAGS & kFlagFourStep) != 0;
     static constexpr bool REALIN = (FLAGS & kFlagRealIn) != 0;
     static constexpr bool REALOUT = (FLAGS & kFlagRealOut) != 0;
@@ -607,7 +593,7 @@ struct PencilPass {
     static constexpr int PADSH = pad_shift();
     static constexpr int LDS_ROW = STRIDED ? (P + 1) : (ROWS + (ROWS >> PADSH) + 1);
     static constexpr int LDS_ELEMS = STRIDED ? ROWS * (P + 1) : P * LDS_ROW;
-    static constexpr int lds_bytes() { return (LDS_ELEMS + (PERSIST ? N : 0)) * 8; }
+    static constexpr int lds_bytes() { return LDS_ELEMS * 8; }
     static constexpr int threads() { return T * P; }
 
     template <int S> struct St {
@@ -696,13 +682,10 @@ struct PencilPass {
         uint32_t il, ol;
     };
 
-    // Twiddle table entry: in LDS for persistent kernels, else in global memory.
+    // Twiddle table entry (global memory, 32-bit offset).
     __device__ __forceinline__ static float2 tw_at(const float2* tw, int i) {
-        if constexpr (PERSIST) return tw[i];
-        else {
-            const f32x2 w = *gload_at<f32x2>(reinterpret_cast<const char*>(tw), (uint32_t)i * 8u);
-            return make_float2(w.x, w.y);
-        }
+        const f32x2 w = *gload_at<f32x2>(reinterpret_cast<const char*>(tw), (uint32_t)i * 8u);
+        return make_float2(w.x, w.y);
     }
 
     template <int S>
@@ -960,10 +943,6 @@ struct PencilPass {
         }
     }
 
-    __device__ __forceinline__ static int64_t num_tiles(const PassArgs& a) {
-        return STRIDED ? ((a.C + P - 1) / P) * a.O1 * a.O2 : (a.C + P - 1) / P;
-    }
-
     // Thread context for tile t.
     __device__ __forceinline__ static Ctx make_ctx(const PassArgs& a, int64_t t) {
         const int tid = threadIdx.x;
@@ -1011,8 +990,6 @@ struct PencilPass {
         }
         return c;
     }
-
-    static constexpr int V0 = St<0>::NB * St<0>::R;   // first-stage inputs per thread
 
     // Whether the contiguous layout's first stage can move its inputs in
     // pairs (decided on the unpaired instance: the butterfly counts are the
@@ -1101,56 +1078,24 @@ struct PencilPass {
     }
 
     __device__ __forceinline__ static void run(const PassArgs& a0, const BatchTable& bt, float2* lds) {
-        if constexpr (!PERSIST) {
-            // A merged batch launch first picks its array; both kinds of
-            // launch then share one pipeline.
-            PassArgs a = a0;
-            int64_t t = (FLAGS & kFlagXcdOrder) ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-            if (bt.count != 0) {
-                int i = 0;
-                while (i + 1 < bt.count && t >= bt.d[i].tile_end) ++i;
-                const ArrayDesc& d = bt.d[i];
-                a.src = d.src;
-                a.dst = d.dst;
-                a.C = d.C;
-                a.O1 = d.O1;
-                a.es_in = a.es_out = d.es;
-                a.os1_in = a.os1_out = d.os1;
-                a.scale = d.scale;
-                t -= i ? bt.d[i - 1].tile_end : 0;
-            }
-            const Ctx c = make_ctx(a, t);
-            float2 v[maxv()];
-            load_first(v, c, a);
-            stages<0>(lds, v, c, a, a.tw);
-        } else {
-            const PassArgs& a = a0;
-            float2* twl = lds + LDS_ELEMS;
-            for (int i = threadIdx.x; i < N; i += T * P) twl[i] = a.tw[i];
-            const int64_t ntiles = num_tiles(a);
-            int64_t t = blockIdx.x;
-            float2 nxt[V0];
-            Ctx cn;
-            if (t < ntiles) {
-                cn = make_ctx(a, t);
-                load_first(nxt, cn, a);
-            }
-            __syncthreads();   // twiddle table visible
-            while (t < ntiles) {
-                const Ctx c = cn;
-                float2 v[maxv()];
-#pragma unroll
-                for (int i = 0; i < V0; ++i) v[i] = nxt[i];
-                const int64_t tn = t + gridDim.x;
-                if (tn < ntiles) {   // prefetch the next tile
-                    cn = make_ctx(a, tn);
-                    load_first(nxt, cn, a);
-                }
-                stages<0>(lds, v, c, a, twl);
-                __syncthreads();     // LDS free for the next tile
-                t = tn;
-            }
+        // A merged batch launch first picks its array; both kinds of launch
+        // then share one pipeline.
+        PassArgs a = a0;
+        int64_t t = blockIdx.x;
+        if (bt.count != 0) {
+            int i = 0;
+            while (i + 1 < bt.count && t >= bt.d[i].tile_end) ++i;
+            const ArrayDesc& d = bt.d[i];
+            a.src = d.src;
+            a.dst = d.dst;
+            a.C = d.C;
+            a.O1 = d.O1;
+            a.es_in = a.es_out = d.es;
+            a.os1_in = a.os1_out = d.os1;
+            a.scale = d.scale;
+            t -= i ? bt.d[i - 1].tile_end : 0;
         }
+        run_tile(a, t, lds);
     }
 };
 
