@@ -29,12 +29,15 @@ constexpr int kPT = kPersistThreads;
 constexpr int kPersistFlags = kPassFlags;
 
 // Geometry in the persistent kernel: one butterfly of the widest radix per
-// thread and exactly kPersistThreads threads per workgroup.  Contiguous
+// thread (two for strided 256-point tiles) and exactly kPersistThreads
+// threads per workgroup.  Contiguous
 // 32-point pencils take radix <= 8 stages, 4 threads per pencil: with one
 // thread per pencil a wave's loads touch 64 cache lines each.
 template <int N, bool ST> struct PGeo {
     static constexpr int PLAN = (!ST && N == 32) ? 2 : 0;
-    static constexpr int T = N / max_radix(make_radices(N, PLAN));
+    // strided 256-point tiles: 8 threads per column, so that a tile spans
+    // 32 columns (256-byte rows) rather than 16
+    static constexpr int T = (ST && N == 256) ? 8 : N / max_radix(make_radices(N, PLAN));
     static constexpr int P = kPT / T;
     static_assert(T * P == kPT, "persistent geometry must fill the workgroup");
     static constexpr int kfor() {
