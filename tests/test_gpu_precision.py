@@ -52,7 +52,12 @@ CASES = [("fp16", 0, 3e-3), ("bf16", 0, 6e-3), ("bf16", 1, 3e-3)]
 
 
 @pytest.mark.parametrize("kind,flags,bound", CASES, ids=["fp16", "bf16", "bf16-fp32tw"])
-@pytest.mark.parametrize("shape", [(64, 64, 64), (96, 32, 128), (32, 1, 1), (256, 256, 1), (8, 2048, 2)],
+# (54, 36, 8) and (48, 54, 24): strided tiles of 32 columns with a ragged
+# last tile of an even column count (y: 22, 16; z of the first: 24);
+# (27, 16, 8): odd y column count and stride, where adjacent columns do not
+# pair, then an even z pass that does
+@pytest.mark.parametrize("shape", [(64, 64, 64), (96, 32, 128), (32, 1, 1), (256, 256, 1), (8, 2048, 2),
+                                   (54, 36, 8), (48, 54, 24), (27, 16, 8)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_small(ws, shape, kind, flags, bound):
     e, fl, p = run_case(ws, shape, kind, flags)
