@@ -225,6 +225,28 @@ def variant_rank(ws, torch, shape, steps, warmup, batch=1, one_launch=False):
     return out
 
 
+def variant_cube1024(ws, torch, steps, warmup):
+    """1024^3 complex64 forward (8 GiB per array): the same kernels at pencils
+    of 1024; the input is drawn on the device (N(0,1), seeded), as a host
+    draw of 2^30 complex values would dominate the bench's run time."""
+    n = 1024
+    N = n ** 3
+    log("variant 1024^3")
+    gen = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randn((n, n, n), dtype=torch.complex64, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    plan = ws.Plan(n, n, n, "c64", -1)
+    ms, per = time_events(lambda: plan.execute(x, y), steps, warmup)
+    passes = bench_plan_passes(plan, x, y, steps, warmup)
+    for p in passes:
+        p["hbm_frac"] = 2 * N * 8 / (p["ms"] * 1e-3) / HBM_PEAK
+    out = {"plan": plan.describe(), "ms": ms, "ms_min": min(per), "GFLOPs": flops(N) / (ms * 1e-3) / 1e9,
+           "hbm_frac": 3 * 2 * N * 8 / (ms * 1e-3) / HBM_PEAK, "passes": passes}
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def variant_poisson(ws, torch, steps, warmup):
     import synth
     n = 256
@@ -345,6 +367,7 @@ def main() -> int:
         variants["2d_8192"] = variant_rank(ws, torch, (8192, 8192, 1), vs, 2)
         variants["1d_65536_x1024"] = variant_rank(ws, torch, (65536, 1, 1), vs, 2, batch=1024)
         variants["32cubed"] = variant_rank(ws, torch, (32, 32, 32), vs, 2, one_launch=True)
+        variants["1024cubed"] = variant_cube1024(ws, torch, vs, 2)
         variants["poisson_256"] = variant_poisson(ws, torch, vs, 2)
     cpu = None
     if not args.no_cpu_baseline:

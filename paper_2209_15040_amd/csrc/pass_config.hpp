@@ -49,9 +49,11 @@ constexpr int cfg_T_contig(int N, int plan = 0) {
 }
 // Contiguous tiles: 256-thread workgroups for complex64; one wave for the
 // 4-byte types, whose tiles carry half the bytes, so more workgroups (and
-// more bytes in flight) fit per CU within the same FP32 LDS budget.
+// more bytes in flight) fit per CU within the same FP32 LDS budget.  The
+// 1024-point complex64 tile is one wave as well (two pencils, 17 KB of LDS:
+// 355 us per GiB against 363-390 us for eight pencils in 256 threads).
 constexpr int cfg_P_contig(int N, int plan = 0, int bytes = 8) {
-    const int p = (bytes == 8 ? 256 : 64) / cfg_T_contig(N, plan);
+    const int p = (bytes == 8 && N != 1024 ? 256 : 64) / cfg_T_contig(N, plan);
     return p < 1 ? 1 : p;
 }
 

@@ -1,4 +1,5 @@
-"""Arrays past the 32-bit lane-offset limit of the split addressing.
+"""Large arrays: past the 32-bit lane-offset limit of the split addressing,
+and the 1024^3 cube.
 
 16384 x 16384 x 2 complex64 (4 GiB): the z pass has a 2 GiB element stride,
 so its per-lane offsets no longer fit 32 bits and it runs the 64-bit
@@ -7,6 +8,9 @@ element-index form of the same kernel.  Checked two ways:
 * the whole transform of a separable input f(x) g(y) h(z), whose DFT is
   exactly F(kx) G(ky) H(kz) (each factor from the oracle's 1D transform), at
   sampled outputs, plus Parseval over the whole output.
+1024^3 complex64 (8 GiB per array; pencils of 1024 in every pass, z stride
+8 MiB) is checked the same two ways: each pass alone on a random input at
+sampled pencils, and the separable whole transform.
 """
 import numpy as np
 import pytest
@@ -80,5 +84,70 @@ def test_whole_transform_separable_input(ws):
     sy = sum(float((y[z].abs().double() ** 2).sum()) for z in range(NZ))
     parseval = abs(sy / (NX * NY * NZ * sx) - 1.0)
     print(f"16384x16384x2 separable: sampled rel_l2 {e:.3e}, Parseval deviation {parseval:.2e} [{p.describe()}]")
+    assert e <= 1e-6
+    assert parseval <= 1e-6
+
+
+CUBE = 1024
+CUBE_SAMPLES = 20_000
+
+
+def _cube_plan(ws):
+    free, _ = torch.cuda.mem_get_info()
+    if free < 20 * 2 ** 30:
+        pytest.skip("needs 20 GiB of free device memory")
+    return ws.Plan(CUBE, CUBE, CUBE, "c64", -1)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2], ids=["x", "y", "z"])
+def test_1024cubed_each_pass_random_input(ws, axis):
+    """Pass `axis` of the 1024^3 plan alone: CUBE_SAMPLES random pencils along
+    that axis against the oracle's 1D transform."""
+    p = _cube_plan(ws)
+    assert p.num_passes == 3, p.describe()
+    gen = torch.Generator(device="cuda").manual_seed(40 + axis)
+    x = torch.randn((CUBE, CUBE, CUBE), dtype=torch.complex64, device="cuda", generator=gen)
+    y = torch.empty_like(x) if axis == 0 else x.clone()   # the y and z passes run in place on the output
+    p.execute_pass(axis, x, y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(41 + axis)
+    i = torch.from_numpy(rng.integers(0, CUBE, CUBE_SAMPLES)).cuda()
+    k = torch.from_numpy(rng.integers(0, CUBE, CUBE_SAMPLES)).cuda()
+    if axis == 0:
+        a, got = x[i, k, :], y[i, k, :]                  # (z, y) fixed, pencils along x
+    elif axis == 1:
+        a, got = x[i, :, k], y[i, :, k]                  # (z, x) fixed, along y
+    else:
+        a, got = x[:, i, k].T, y[:, i, k].T              # (y, x) fixed, along z
+    a = a.cpu().numpy().astype(np.complex128)
+    got = got.cpu().numpy()
+    del x, y
+    torch.cuda.empty_cache()
+    want = oracle.fft1d_batch(np.ascontiguousarray(a), -1)
+    e = rel_l2(got, want)
+    print(f"1024^3 pass {axis}: {CUBE_SAMPLES} pencils, rel_l2 {e:.3e} [{p.describe()}]")
+    assert e <= 1e-6
+
+
+def test_1024cubed_separable(ws):
+    p = _cube_plan(ws)
+    f = synth.normal_c((CUBE,), seed=43).astype(np.complex64)
+    g = synth.normal_c((CUBE,), seed=44).astype(np.complex64)
+    h = synth.normal_c((CUBE,), seed=45).astype(np.complex64)
+    x = (torch.from_numpy(h).cuda()[:, None, None] * torch.from_numpy(g).cuda()[None, :, None]) * \
+        torch.from_numpy(f).cuda()[None, None, :]
+    y = torch.empty_like(x)
+    p.execute(x, y)
+    torch.cuda.synchronize()
+    F, G, H = (oracle.fft1d_batch(v.astype(np.complex128)[None], -1)[0] for v in (f, g, h))
+    rng = np.random.default_rng(46)
+    kz, ky, kx = (rng.integers(0, CUBE, SAMPLES) for _ in range(3))
+    got = y[torch.from_numpy(kz).cuda(), torch.from_numpy(ky).cuda(), torch.from_numpy(kx).cuda()].cpu().numpy()
+    want = H[kz] * G[ky] * F[kx]
+    e = rel_l2(got, want)
+    sx = sum(float((x[z].abs().double() ** 2).sum()) for z in range(CUBE))
+    sy = sum(float((y[z].abs().double() ** 2).sum()) for z in range(CUBE))
+    parseval = abs(sy / (CUBE ** 3 * sx) - 1.0)
+    print(f"1024^3 separable: sampled rel_l2 {e:.3e}, Parseval deviation {parseval:.2e}")
     assert e <= 1e-6
     assert parseval <= 1e-6
