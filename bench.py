@@ -363,6 +363,7 @@ def main() -> int:
         variants["fp16"] = variant_c16(ws, torch, "fp16", vs, 2)
         variants["bf16"] = variant_c16(ws, torch, "bf16", vs, 2)
         variants["bf16_fp32_twiddles"] = variant_c16(ws, torch, "bf16", vs, 2, ws.FLAG_FP32_TWIDDLES)
+        variants["fp16_math"] = variant_c16(ws, torch, "fp16", vs, 2, ws.FLAG_FP16_MATH)
         variants["batched_96"] = variant_batched(ws, torch, vs, 2)
         variants["2d_8192"] = variant_rank(ws, torch, (8192, 8192, 1), vs, 2)
         variants["1d_65536_x1024"] = variant_rank(ws, torch, (65536, 1, 1), vs, 2, batch=1024)

@@ -26,8 +26,8 @@
  *
  * Reduced precision: each pass p of a 16-bit plan multiplies its output by
  * 2^-s_p with s_p = ceil(log2(n_p) / 2), so the stored result is
- * 2^-S * DFT(a) with S = sum of s_p (wsfft_plan_scale_log2).  WSFFT_C64 plans
- * have S = 0.
+ * 2^-S * DFT(a) with S = sum of s_p (wsfft_plan_scale_log2), and the inverse
+ * (wsfft_execute_inverse) undoes it.  WSFFT_C64 plans have S = 0.
  *
  * Errors: every call validates its arguments before touching the device and
  * returns a status; wsfft_plan_create* return NULL and record the status for
@@ -83,6 +83,13 @@ typedef enum {
 /* Plan flags for wsfft_plan_create_ex. */
 #define WSFFT_FLAG_FP32_TWIDDLES 1u   /* 16-bit plans: keep twiddles in FP32 */
 #define WSFFT_FLAG_TUNE 2u            /* time each pass's kernel variants at creation */
+/* WSFFT_C16_FP16 plans only (else WSFFT_ERROR_INVALID_VALUE): butterflies in
+ * packed FP16 arithmetic instead of FP32, as in the paper's FP16 runs (§4.1,
+ * §5.1).  Values stay FP16 pairs in registers and LDS; each pass scales its
+ * loaded values by its 2^-s_p (so the output is the same 2^-S * DFT as
+ * without the flag) and every arithmetic step rounds to FP16.  Twiddles are
+ * FP16 whatever WSFFT_FLAG_FP32_TWIDDLES says. */
+#define WSFFT_FLAG_FP16_MATH 4u
 
 /*
  * Autotuning.  Passes of the hot lengths (powers of two up to 1024 strided,
@@ -125,8 +132,11 @@ wsfft_status_t wsfft_execute(wsfft_plan_t plan, const void* in, void* out, hipSt
  * the steps with conjugated roots. */
 wsfft_status_t wsfft_execute_adjoint(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream);
 
-/* out = 2^-S / N * sum with the opposite sign: the inverse of wsfft_execute
- * (Section 4.2), with the 1/N folded into the last pass. */
+/* out = 2^S / N * sum with the opposite sign: the inverse of wsfft_execute
+ * (Section 4.2), wsfft_execute_inverse(wsfft_execute(a)) = a.  C64 plans
+ * (S = 0) fold the 1/N into the last pass; 16-bit plans scale pass p by
+ * 2^s_p / n_p (about 1/sqrt(n_p), like the forward 2^-s_p), which keeps every
+ * stored value in range. */
 wsfft_status_t wsfft_execute_inverse(wsfft_plan_t plan, const void* in, void* out, hipStream_t stream);
 
 /*

@@ -29,6 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libwsfft.so")
 C64, C16_FP16, C16_BF16 = 0, 1, 2
 FLAG_FP32_TWIDDLES = 1
 FLAG_TUNE = 2
+FLAG_FP16_MATH = 4       # FP16 plans: packed FP16 butterfly arithmetic
 DTYPES = {"c64": C64, "fp16": C16_FP16, "bf16": C16_BF16}
 _TORCH_DTYPE = {C64: torch.complex64, C16_FP16: torch.float16, C16_BF16: torch.bfloat16}
 
@@ -183,7 +184,8 @@ class Plan:
         return self._run(_execute_adjoint, x, out, stream, "execute_adjoint")
 
     def execute_inverse(self, x, out=None, stream=None):
-        """out = 2^-S / N * DFT with the opposite sign."""
+        """out = 2^S / N * DFT with the opposite sign: the exact inverse of
+        ``execute`` (S = 0 for complex64)."""
         return self._run(_execute_inverse, x, out, stream, "execute_inverse")
 
     def execute_pass(self, index: int, x, out, mode: int = 0, stream=None):

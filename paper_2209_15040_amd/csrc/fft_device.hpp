@@ -39,26 +39,76 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 template <int SIGN> __device__ __forceinline__ float2 crot90(float2 a) {
     return SIGN < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
 }
+__device__ __forceinline__ float2 cneg(float2 a) { return make_float2(-a.x, -a.y); }
+// v + s*t
+__device__ __forceinline__ float2 cfma_s(float2 t, float s, float2 v) {
+    return make_float2(fmaf(s, t.x, v.x), fmaf(s, t.y, v.y));
+}
+// a * h*(sr + i*si) with sr, si = +-1 (an eighth turn when h = 1/sqrt(2))
+template <bool RP, bool IP> __device__ __forceinline__ float2 crot45(float2 a, float h) {
+    const float ax = a.x, ay = a.y;
+    const float re = (RP ? ax : -ax) - (IP ? ay : -ay);
+    const float im = (IP ? ax : -ax) + (RP ? ay : -ay);
+    return make_float2(h * re, h * im);
+}
+template <class C> __device__ __forceinline__ C cconst(double re, double im);
+template <> __device__ __forceinline__ float2 cconst<float2>(double re, double im) {
+    return make_float2((float)re, (float)im);
+}
+
+// The same operations on packed FP16 pairs (re in the low half): one packed
+// instruction per complex add, two per complex multiply.
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h16x2 hswap(h16x2 a) { return __builtin_shufflevector(a, a, 1, 0); }
+__device__ __forceinline__ h16x2 hsplat(_Float16 x) { return (h16x2){x, x}; }
+__device__ __forceinline__ h16x2 cadd(h16x2 a, h16x2 b) { return a + b; }
+__device__ __forceinline__ h16x2 csub(h16x2 a, h16x2 b) { return a - b; }
+__device__ __forceinline__ h16x2 cneg(h16x2 a) { return -a; }
+__device__ __forceinline__ h16x2 cmul(h16x2 a, h16x2 w) {
+    // (a.x w.x - a.y w.y, a.y w.x + a.x w.y)
+    const h16x2 wi = (h16x2){-w.y, w.y};
+    return __builtin_elementwise_fma(hswap(a), wi, a * hsplat(w.x));
+}
+__device__ __forceinline__ h16x2 cscale(h16x2 a, float s) { return a * hsplat((_Float16)s); }
+template <int SIGN> __device__ __forceinline__ h16x2 crot90(h16x2 a) {
+    const h16x2 b = hswap(a);
+    return SIGN < 0 ? b * (h16x2){1, -1} : b * (h16x2){-1, 1};
+}
+__device__ __forceinline__ h16x2 cfma_s(h16x2 t, float s, h16x2 v) {
+    return __builtin_elementwise_fma(t, hsplat((_Float16)s), v);
+}
+template <bool RP, bool IP> __device__ __forceinline__ h16x2 crot45(h16x2 a, float h) {
+    const _Float16 r = (_Float16)(RP ? h : -h), i = (_Float16)(IP ? h : -h);
+    return __builtin_elementwise_fma(hswap(a), (h16x2){-i, i}, a * hsplat(r));
+}
+template <> __device__ __forceinline__ h16x2 cconst<h16x2>(double re, double im) {
+    return (h16x2){(_Float16)re, (_Float16)im};
+}
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// A table entry (FP32 pair) as a register value.
+template <class C> __device__ __forceinline__ C cvt_value(f32x2 w);
+template <> __device__ __forceinline__ float2 cvt_value<float2>(f32x2 w) { return make_float2(w.x, w.y); }
+template <> __device__ __forceinline__ h16x2 cvt_value<h16x2>(f32x2 w) { return __builtin_convertvector(w, h16x2); }
 
 // ------------------------------------------------------- small-radix DFTs ---
 // In-place R-point DFT of v[0..R) with kernel exp(SIGN * 2*pi*i*j*k/R).
 template <int R, int SIGN> struct Dft;
 
 template <int SIGN> struct Dft<2, SIGN> {
-    static __device__ __forceinline__ void run(float2* v) {
-        const float2 a = v[0], b = v[1];
+    template <class C> static __device__ __forceinline__ void run(C* v) {
+        const C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     }
 };
 
 template <int SIGN> struct Dft<3, SIGN> {
-    static __device__ __forceinline__ void run(float2* v) {
+    template <class C> static __device__ __forceinline__ void run(C* v) {
         const float h = 0.86602540378443864676f;   // sin(2*pi/3)
-        const float2 t = cadd(v[1], v[2]);
-        const float2 d = csub(v[1], v[2]);
-        const float2 m = make_float2(fmaf(-0.5f, t.x, v[0].x), fmaf(-0.5f, t.y, v[0].y));
-        const float2 r = crot90<SIGN>(cscale(d, h));   // SIGN*i*sin(2pi/3)*d
+        const C t = cadd(v[1], v[2]);
+        const C d = csub(v[1], v[2]);
+        const C m = cfma_s(t, -0.5f, v[0]);
+        const C r = crot90<SIGN>(cscale(d, h));   // SIGN*i*sin(2pi/3)*d
         v[0] = cadd(v[0], t);
         v[1] = cadd(m, r);
         v[2] = csub(m, r);
@@ -66,9 +116,9 @@ template <int SIGN> struct Dft<3, SIGN> {
 };
 
 template <int SIGN> struct Dft<4, SIGN> {
-    static __device__ __forceinline__ void run(float2* v) {
-        const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-        const float2 t2 = cadd(v[1], v[3]), t3 = crot90<SIGN>(csub(v[1], v[3]));
+    template <class C> static __device__ __forceinline__ void run(C* v) {
+        const C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        const C t2 = cadd(v[1], v[3]), t3 = crot90<SIGN>(csub(v[1], v[3]));
         v[0] = cadd(t0, t2);
         v[2] = csub(t0, t2);
         v[1] = cadd(t1, t3);
@@ -78,18 +128,16 @@ template <int SIGN> struct Dft<4, SIGN> {
 
 // 8 = 2 x 4: even/odd 4-point DFTs, odd part twiddled by W_8^k.
 template <int SIGN> struct Dft<8, SIGN> {
-    static __device__ __forceinline__ void run(float2* v) {
+    template <class C> static __device__ __forceinline__ void run(C* v) {
         const float c = 0.70710678118654752440f;
-        float2 e[4] = {v[0], v[2], v[4], v[6]};
-        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        C e[4] = {v[0], v[2], v[4], v[6]};
+        C o[4] = {v[1], v[3], v[5], v[7]};
         Dft<4, SIGN>::run(e);
         Dft<4, SIGN>::run(o);
         // W_8^1 = c*(1 + SIGN*i), W_8^2 = SIGN*i, W_8^3 = c*(-1 + SIGN*i)
-        o[1] = SIGN < 0 ? make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x))
-                        : make_float2(c * (o[1].x - o[1].y), c * (o[1].y + o[1].x));
+        o[1] = crot45<true, (SIGN > 0)>(o[1], c);
         o[2] = crot90<SIGN>(o[2]);
-        o[3] = SIGN < 0 ? make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y))
-                        : make_float2(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y));
+        o[3] = crot45<false, (SIGN > 0)>(o[3], c);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             v[k] = cadd(e[k], o[k]);
@@ -144,27 +192,24 @@ constexpr CosSin root_cs(int m, int R) {
 
 // a * W_R^M with W_R = exp(SIGN*2*pi*i/R); quarter turns are exact swaps,
 // eighth turns cost one multiply per component.
-template <int R, int M, int SIGN>
-__device__ __forceinline__ float2 twc(float2 a) {
+template <int R, int M, int SIGN, class C>
+__device__ __forceinline__ C twc(C a) {
     constexpr int m = M % R;
     if constexpr (m == 0) {
         return a;
     } else if constexpr ((4 * m) % R == 0) {
         constexpr int q = 4 * m / R;
         if constexpr (q == 1) return crot90<SIGN>(a);
-        else if constexpr (q == 2) return make_float2(-a.x, -a.y);
+        else if constexpr (q == 2) return cneg(a);
         else return crot90<-SIGN>(a);
     } else if constexpr ((8 * m) % R == 0) {
         constexpr CosSin w = root_cs(m, R);
         constexpr float h = 0.70710678118654752440f;
         constexpr bool cp = w.c > 0, sp = (SIGN * w.s) > 0;   // signs of re, im of W
-        const float ax = a.x, ay = a.y;
-        const float re = (cp ? ax : -ax) - (sp ? ay : -ay);
-        const float im = (sp ? ax : -ax) + (cp ? ay : -ay);
-        return make_float2(h * re, h * im);
+        return crot45<cp, sp>(a, h);
     } else {
         constexpr CosSin w = root_cs(m, R);
-        return cmul(a, make_float2((float)w.c, (float)(SIGN * w.s)));
+        return cmul(a, cconst<C>(w.c, SIGN * w.s));
     }
 }
 
@@ -172,19 +217,19 @@ __device__ __forceinline__ float2 twc(float2 a) {
 //   X[k1 + R1*k2] = sum_n2 W_R2^(n2 k2) W_R^(n2 k1) sum_n1 x[R2 n1 + n2] W_R1^(n1 k1)
 template <int R1, int R2, int SIGN> struct DftComp {
     static constexpr int R = R1 * R2;
-    template <int I>
-    static __device__ __forceinline__ void twiddle(float2* y) {
+    template <int I, class C>
+    static __device__ __forceinline__ void twiddle(C* y) {
         if constexpr (I < R) {
             constexpr int n2 = I / R1, k1 = I % R1;
             y[I] = twc<R, n2 * k1, SIGN>(y[I]);
             twiddle<I + 1>(y);
         }
     }
-    static __device__ __forceinline__ void run(float2* v) {
-        float2 y[R];
+    template <class C> static __device__ __forceinline__ void run(C* v) {
+        C y[R];
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) {
-            float2 u[R1];
+            C u[R1];
 #pragma unroll
             for (int n1 = 0; n1 < R1; ++n1) u[n1] = v[R2 * n1 + n2];
             Dft<R1, SIGN>::run(u);
@@ -194,7 +239,7 @@ template <int R1, int R2, int SIGN> struct DftComp {
         twiddle<0>(y);
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) {
-            float2 w[R2];
+            C w[R2];
 #pragma unroll
             for (int n2 = 0; n2 < R2; ++n2) w[n2] = y[n2 * R1 + k1];
             Dft<R2, SIGN>::run(w);
@@ -294,7 +339,6 @@ constexpr int stage_tw_offset(const Radices& R, int s) {
 // All pass data lives in device (global) memory; the explicit address space
 // keeps accesses as global loads/stores even in code that is not inlined into
 // a kernel, where pointers would otherwise be generic (flat).
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <class T> using gptr = __attribute__((address_space(1))) T*;
 template <class T> using gcptr = const __attribute__((address_space(1))) T*;
@@ -311,6 +355,8 @@ template <class T> __device__ __forceinline__ gptr<T> gstore_at(char* base, uint
 
 
 struct IoC64 {   // complex64: FP32 re, FP32 im
+    using value_type = float2;
+    static constexpr bool scale_at_load = false;
     static constexpr int bytes = 8;
     static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
         const f32x2 v = gload_ptr<f32x2>(p)[i];
@@ -369,6 +415,8 @@ struct IoC64 {   // complex64: FP32 re, FP32 im
 };
 
 struct IoF16 {   // FP16 re, FP16 im
+    using value_type = float2;
+    static constexpr bool scale_at_load = false;
     static constexpr int bytes = 4;
     static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
         const uint32_t w = gload_ptr<uint32_t>(p)[i];
@@ -415,6 +463,54 @@ struct IoF16 {   // FP16 re, FP16 im
     }
 };
 
+// FP16 storage with FP16 arithmetic: values stay packed FP16 pairs in
+// registers and LDS (4 bytes per element), so a tile holds half the state of
+// the FP32-arithmetic types; loads and stores need no conversion.
+struct IoF16M {
+    using value_type = h16x2;
+    static constexpr bool scale_at_load = true;
+    static constexpr int bytes = 4;
+    static __device__ __forceinline__ h16x2 load(const void* p, int64_t i) {
+        return __builtin_bit_cast(h16x2, gload_ptr<uint32_t>(p)[i]);
+    }
+    static __device__ __forceinline__ void store(void* p, int64_t i, h16x2 v) {
+        gstore_ptr<uint32_t>(p)[i] = __builtin_bit_cast(uint32_t, v);
+    }
+    static __device__ __forceinline__ h16x2 load_nt(const void* p, int64_t i) {
+        return __builtin_bit_cast(h16x2, __builtin_nontemporal_load(gload_ptr<uint32_t>(p) + i));
+    }
+    static __device__ __forceinline__ void store_nt(void* p, int64_t i, h16x2 v) {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, v), gstore_ptr<uint32_t>(p) + i);
+    }
+    static __device__ __forceinline__ void load2_nt(const void* p, int64_t i, h16x2& a, h16x2& b) {
+        const uint64_t w = __builtin_nontemporal_load(gload_ptr<uint64_t>(p) + i / 2);
+        a = __builtin_bit_cast(h16x2, (uint32_t)w);
+        b = __builtin_bit_cast(h16x2, (uint32_t)(w >> 32));
+    }
+    static __device__ __forceinline__ void store2_nt(void* p, int64_t i, h16x2 a, h16x2 b) {
+        const uint64_t w = (uint64_t)__builtin_bit_cast(uint32_t, a) | ((uint64_t)__builtin_bit_cast(uint32_t, b) << 32);
+        __builtin_nontemporal_store(w, gstore_ptr<uint64_t>(p) + i / 2);
+    }
+    template <bool NT> static __device__ __forceinline__ h16x2 ld(const char* b, uint32_t off) {
+        return __builtin_bit_cast(h16x2, NT ? __builtin_nontemporal_load(gload_at<uint32_t>(b, off))
+                                            : *gload_at<uint32_t>(b, off));
+    }
+    template <bool NT> static __device__ __forceinline__ void st(char* b, uint32_t off, h16x2 v) {
+        const uint32_t w = __builtin_bit_cast(uint32_t, v);
+        if (NT) __builtin_nontemporal_store(w, gstore_at<uint32_t>(b, off));
+        else *gstore_at<uint32_t>(b, off) = w;
+    }
+    static __device__ __forceinline__ void ld2_nt(const char* b, uint32_t off, h16x2& x, h16x2& y) {
+        const uint64_t w = __builtin_nontemporal_load(gload_at<uint64_t>(b, off));
+        x = __builtin_bit_cast(h16x2, (uint32_t)w);
+        y = __builtin_bit_cast(h16x2, (uint32_t)(w >> 32));
+    }
+    static __device__ __forceinline__ void st2_nt(char* b, uint32_t off, h16x2 x, h16x2 y) {
+        __builtin_nontemporal_store((uint64_t)__builtin_bit_cast(uint32_t, x) | ((uint64_t)__builtin_bit_cast(uint32_t, y) << 32),
+                                    gstore_at<uint64_t>(b, off));
+    }
+};
+
 // BF16 = top 16 bits of an FP32; storage rounds to nearest even, both
 // components in one conversion (v_cvt_pk_bf16_f32 on gfx950).
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -426,6 +522,8 @@ __device__ __forceinline__ uint32_t f32x2_to_bf16x2_rne(float re, float im) {
 }
 
 struct IoBF16 {  // BF16 re (low half), BF16 im (high half)
+    using value_type = float2;
+    static constexpr bool scale_at_load = false;
     static constexpr int bytes = 4;
     static __device__ __forceinline__ float2 load(const void* p, int64_t i) {
         const uint32_t w = gload_ptr<uint32_t>(p)[i];
@@ -540,6 +638,12 @@ struct BatchTable {
 // 1/K of its size in LDS and more workgroups stay resident per CU.
 template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1, int PLAN = 0>
 struct PencilPass {
+    // register and LDS value of one complex element: FP32 pairs, or packed
+    // FP16 pairs for the FP16-arithmetic storage type
+    using V = typename IO::value_type;
+    // FP16 arithmetic applies the pass scale to the loaded values, so
+    // intermediate sums stay within the FP16 range
+    static constexpr bool SCALE_IN = IO::scale_at_load;
     static_assert(N % K == 0, "K must divide N");
     static constexpr bool NT = (FLAGS & kFlagNontemporal) != 0;
     static constexpr bool FOURSTEP = (FLAGS & kFlagFourStep) != 0;
@@ -550,37 +654,37 @@ struct PencilPass {
     static_assert(!(REALOUT || POISSON) || (STRIDED && !FOURSTEP), "fused outputs are strided direct passes");
     static constexpr int64_t BI = REALIN ? 4 : IO::bytes;    // bytes per input element
     static constexpr int64_t BO = REALOUT ? 4 : IO::bytes;   // bytes per output element
-    __device__ __forceinline__ static float2 gload(const void* p, int64_t i) {
+    __device__ __forceinline__ static V gload(const void* p, int64_t i) {
         if constexpr (NT) return IO::load_nt(p, i);
         else return IO::load(p, i);
     }
-    __device__ __forceinline__ static void gstore(void* p, int64_t i, float2 v) {
+    __device__ __forceinline__ static void gstore(void* p, int64_t i, V v) {
         if constexpr (NT) IO::store_nt(p, i, v);
         else IO::store(p, i, v);
     }
     // first-pass input and last-pass output, real where the fused flags say so
-    __device__ __forceinline__ static float2 gload_in(const void* p, int64_t i) {
+    __device__ __forceinline__ static V gload_in(const void* p, int64_t i) {
         if constexpr (REALIN) return make_float2(__builtin_nontemporal_load(gload_ptr<float>(p) + i), 0.f);
         else return gload(p, i);
     }
-    __device__ __forceinline__ static void gstore_out(void* p, int64_t i, float2 v) {
+    __device__ __forceinline__ static void gstore_out(void* p, int64_t i, V v) {
         if constexpr (REALOUT) __builtin_nontemporal_store(v.x, gstore_ptr<float>(p) + i);
         else gstore(p, i, v);
     }
-    __device__ __forceinline__ static float2 ld_in(const char* b, uint32_t off) {
+    __device__ __forceinline__ static V ld_in(const char* b, uint32_t off) {
         if constexpr (REALIN) return make_float2(__builtin_nontemporal_load(gload_at<float>(b, off)), 0.f);
         else return IO::template ld<NT>(b, off);
     }
-    __device__ __forceinline__ static void st_out(char* b, uint32_t off, float2 v) {
+    __device__ __forceinline__ static void st_out(char* b, uint32_t off, V v) {
         if constexpr (REALOUT) __builtin_nontemporal_store(v.x, gstore_at<float>(b, off));
         else IO::template st<NT>(b, off, v);
     }
     static constexpr Radices RD = make_radices(N, PLAN);
     static constexpr int NS = RD.n;
     static constexpr int ROWS = N / K;   // LDS rows per exchange round
-    // LDS layout: strided tiles store [element][column] with one float2 of
+    // LDS layout: strided tiles store [element][column] with one V of
     // padding per row; contiguous tiles store [pencil][element] with one
-    // float2 of padding after every 2^PADSH elements, which spreads the
+    // V of padding after every 2^PADSH elements, which spreads the
     // radix-stride writes of the first stages over all banks.
     static constexpr bool PAIRS = !STRIDED && (FLAGS & kFlagPairs) != 0;
     // first-stage writes land R0 (times the slots per thread, when paired)
@@ -593,7 +697,7 @@ struct PencilPass {
     static constexpr int PADSH = pad_shift();
     static constexpr int LDS_ROW = STRIDED ? (P + 1) : (ROWS + (ROWS >> PADSH) + 1);
     static constexpr int LDS_ELEMS = STRIDED ? ROWS * (P + 1) : P * LDS_ROW;
-    static constexpr int lds_bytes() { return LDS_ELEMS * 8; }
+    static constexpr int lds_bytes() { return LDS_ELEMS * (int)sizeof(V); }
     static constexpr int threads() { return T * P; }
 
     template <int S> struct St {
@@ -683,25 +787,29 @@ struct PencilPass {
     };
 
     // Twiddle table entry (global memory, 32-bit offset).
-    __device__ __forceinline__ static float2 tw_at(const float2* tw, int i) {
-        const f32x2 w = *gload_at<f32x2>(reinterpret_cast<const char*>(tw), (uint32_t)i * 8u);
-        return make_float2(w.x, w.y);
+    __device__ __forceinline__ static V tw_at(const float2* tw, int i) {
+        return cvt_value<V>(*gload_at<f32x2>(reinterpret_cast<const char*>(tw), (uint32_t)i * 8u));
+    }
+    // The stored value: the pass scale, unless it was applied at the load.
+    __device__ __forceinline__ static V oscale(V v, const PassArgs& a) {
+        if constexpr (SCALE_IN) return v;
+        else return cscale(v, a.scale);
     }
 
     template <int S>
-    __device__ __forceinline__ static void butterflies(float2* v, int j, const float2* tw) {
+    __device__ __forceinline__ static void butterflies(V* v, int j, const float2* tw) {
         using Q = St<S>;
 #pragma unroll
         for (int t = 0; t < Q::NB; ++t) {
             const int b = Q::bf(j, t);
             if (!Q::FULL && b >= Q::NBF) continue;
-            float2* u = v + t * Q::R;
+            V* u = v + t * Q::R;
             if (S > 0) {
                 const int k = b % Q::Ns;
                 constexpr int off = stage_tw_offset(RD, S);
 #pragma unroll
                 for (int r = 1; r < Q::R; ++r) {
-                    float2 w = tw_at(tw, off + (r - 1) * Q::Ns + k);
+                    V w = tw_at(tw, off + (r - 1) * Q::Ns + k);
                     if (SIGN > 0) w.y = -w.y;
                     u[r] = cmul(u[r], w);
                 }
@@ -713,7 +821,7 @@ struct PencilPass {
     // Stage S outputs (vo) -> stage S+1 inputs (vi) through LDS, in K rounds
     // of ROWS rows.  lead: the LDS may still be read by the previous exchange.
     template <int S>
-    __device__ __forceinline__ static void exchange(float2* lds, const float2* vo, float2* vi, int p, int j,
+    __device__ __forceinline__ static void exchange(V* lds, const V* vo, V* vi, int p, int j,
                                                     bool lead) {
         using Q = St<S>;
         using Q2 = St<S + 1>;
@@ -755,10 +863,10 @@ struct PencilPass {
     // output position, entry g*N + e, so lanes with consecutive e read
     // consecutive entries; mode 2 (g = o1, the same for the whole tile) reads
     // the plain table W_M^m at m = g*e.
-    __device__ __forceinline__ static float2 tw4_of(int e, int64_t col, int64_t o1, const PassArgs& a) {
+    __device__ __forceinline__ static V tw4_of(int e, int64_t col, int64_t o1, const PassArgs& a) {
         const uint32_t m = a.tw4_mode == 1 ? (uint32_t)col * N + e : (uint32_t)o1 * e;   // < M <= 2^20
         const f32x2 wv = *gload_at<f32x2>(reinterpret_cast<const char*>(a.tw4), m * 8u);
-        float2 w = make_float2(wv.x, wv.y);
+        V w = cvt_value<V>(wv);
         if (SIGN > 0) w.y = -w.y;
         return w;
     }
@@ -776,8 +884,8 @@ struct PencilPass {
     }
     // A stored value: the pass scale and, for the Poisson z pass, -1/|k|^2 of
     // output element e (its kz index), 0 at k = 0.
-    __device__ __forceinline__ static float2 finish(float2 v, int e, float kxy2, const PassArgs& a) {
-        v = cscale(v, a.scale);
+    __device__ __forceinline__ static V finish(V v, int e, float kxy2, const PassArgs& a) {
+        v = oscale(v, a);
         if constexpr (POISSON) {
             const float kz = wavenumber(e, N);
             const float k2 = kxy2 + kz * kz;
@@ -788,7 +896,7 @@ struct PencilPass {
     }
 
     template <int S>
-    __device__ __forceinline__ static void store_last(float2* lds, const float2* v, const Ctx& c,
+    __device__ __forceinline__ static void store_last(V* lds, const V* v, const Ctx& c,
                                                       const PassArgs& a) {
         using Q = St<S>;
         if (FOURSTEP && STRIDED && a.tstore) {
@@ -821,7 +929,7 @@ struct PencilPass {
                 // each thread stores PER elements of this round; their
                 // twiddles are all requested before the first use
                 constexpr int PER = (ROWS * P + T * P - 1) / (T * P);
-                float2 w4[PER];
+                V w4[PER];
                 if (FOURSTEP && a.tw4_mode != 0) {
 #pragma unroll
                     for (int i = 0; i < PER; ++i) {
@@ -831,9 +939,10 @@ struct PencilPass {
                         const uint32_t m = a.tw4_mode == 1 ? (uint32_t)pl * N + e : o1w * e;
                         if (idx < ROWS * P && c0 + pl < a.C) {
                             const f32x2 wv = *gload_at<f32x2>(twbase, m * 8u);
-                            w4[i] = make_float2(wv.x, SIGN > 0 ? -wv.y : wv.y);
+                            w4[i] = cvt_value<V>(wv);
+                            if (SIGN > 0) w4[i].y = -w4[i].y;
                         } else {
-                            w4[i] = make_float2(1.f, 0.f);
+                            w4[i] = cconst<V>(1.0, 0.0);
                         }
                     }
                 }
@@ -845,10 +954,10 @@ struct PencilPass {
                     const int pl = idx / ROWS, el = idx % ROWS, e = el + h * ROWS;
                     const int64_t col = c0 + pl;
                     if (col >= a.C) continue;
-                    float2 x = lds[lidx(pl, el)];
+                    V x = lds[lidx(pl, el)];
                     if (FOURSTEP && a.tw4_mode != 0) x = cmul(x, w4[i]);
-                    if (fit) IO::template st<NT>(obase, (uint32_t)pl * cs32 + (uint32_t)e * es32, cscale(x, a.scale));
-                    else gstore(a.dst, b0 + pl * a.cs_out + (int64_t)e * a.es_out, cscale(x, a.scale));
+                    if (fit) IO::template st<NT>(obase, (uint32_t)pl * cs32 + (uint32_t)e * es32, oscale(x, a));
+                    else gstore(a.dst, b0 + pl * a.cs_out + (int64_t)e * a.es_out, oscale(x, a));
                 }
             }
             return;
@@ -857,14 +966,14 @@ struct PencilPass {
         const int64_t es = STRIDED ? a.es_out : 1;
         if (FOURSTEP && a.tw4_mode != 0) {
             // all twiddle requests first, then the stores
-            float2 w4[Q::NB * Q::R];
+            V w4[Q::NB * Q::R];
 #pragma unroll
             for (int t = 0; t < Q::NB; ++t) {
                 const int b = Q::bf(c.j, t);
 #pragma unroll
                 for (int r = 0; r < Q::R; ++r)
                     w4[t * Q::R + r] = (Q::FULL || b < Q::NBF) ? tw4_of(b + r * Q::NBF, c.col, c.o1, a)
-                                                               : make_float2(1.f, 0.f);
+                                                               : cconst<V>(1.0, 0.0);
             }
 #pragma unroll
             for (int t = 0; t < Q::NB; ++t) {
@@ -874,7 +983,7 @@ struct PencilPass {
                 for (int r = 0; r < Q::R; ++r) {
                     const int e = b + r * Q::NBF;
                     gstore(a.dst, c.base_out + (int64_t)e * es,
-                           cscale(cmul(v[t * Q::R + r], w4[t * Q::R + r]), a.scale));
+                           oscale(cmul(v[t * Q::R + r], w4[t * Q::R + r]), a));
                 }
             }
             return;
@@ -886,8 +995,8 @@ struct PencilPass {
                     for (int t = 0; t < Q::NB; t += 2)
 #pragma unroll
                         for (int r = 0; r < Q::R; ++r)
-                            IO::st2_nt(c.ob + (int64_t)eoff<S>(t, r) * c.oes, c.ol, cscale(v[t * Q::R + r], a.scale),
-                                       cscale(v[(t + 1) * Q::R + r], a.scale));
+                            IO::st2_nt(c.ob + (int64_t)eoff<S>(t, r) * c.oes, c.ol, oscale(v[t * Q::R + r], a),
+                                       oscale(v[(t + 1) * Q::R + r], a));
                     return;
                 }
             }
@@ -910,8 +1019,8 @@ struct PencilPass {
                     const int b = Q::bf(c.j, t);
 #pragma unroll
                     for (int r = 0; r < Q::R; ++r)
-                        IO::store2_nt(a.dst, c.base_out + b + r * Q::NBF, cscale(v[t * Q::R + r], a.scale),
-                                      cscale(v[(t + 1) * Q::R + r], a.scale));
+                        IO::store2_nt(a.dst, c.base_out + b + r * Q::NBF, oscale(v[t * Q::R + r], a),
+                                      oscale(v[(t + 1) * Q::R + r], a));
                 }
                 return;
             }
@@ -931,11 +1040,11 @@ struct PencilPass {
 
     // Stages S .. NS-1; v holds the inputs of stage S.
     template <int S>
-    __device__ __forceinline__ static void stages(float2* lds, float2* v, const Ctx& c, const PassArgs& a,
+    __device__ __forceinline__ static void stages(V* lds, V* v, const Ctx& c, const PassArgs& a,
                                                   const float2* tw) {
         butterflies<S>(v, c.j, tw);
         if constexpr (S + 1 < NS) {
-            float2 w[maxv()];
+            V w[maxv()];
             exchange<S>(lds, v, w, c.p, c.j, S > 0);
             stages<S + 1>(lds, w, c, a, tw);
         } else {
@@ -1013,7 +1122,7 @@ struct PencilPass {
         return PAIRS ? t + r * St<S>::NBF : t * T + r * St<S>::NBF;
     }
 
-    __device__ __forceinline__ static void load_first(float2* v, const Ctx& c, const PassArgs& a) {
+    __device__ __forceinline__ static void load_first(V* v, const Ctx& c, const PassArgs& a) {
         using Q = St<0>;
         if (c.split) {
             if constexpr (pairable<0>()) {
@@ -1056,28 +1165,38 @@ struct PencilPass {
 #pragma unroll
             for (int r = 0; r < Q::R; ++r)
                 v[t * Q::R + r] = c.valid ? gload_in(a.src, c.base_in + (int64_t)(b + r * Q::NBF) * es)
-                                          : make_float2(0.f, 0.f);
+                                          : cconst<V>(0.0, 0.0);
+        }
+    }
+
+    __device__ __forceinline__ static void scale_loaded(V* v, const PassArgs& a) {
+        if constexpr (SCALE_IN) {
+            using Q = St<0>;
+#pragma unroll
+            for (int i = 0; i < Q::NB * Q::R; ++i) v[i] = cscale(v[i], a.scale);
         }
     }
 
     // One tile; the caller owns the LDS and synchronises before reusing it.
-    __device__ __forceinline__ static void run_tile(const PassArgs& a, int64_t t, float2* lds) {
+    __device__ __forceinline__ static void run_tile(const PassArgs& a, int64_t t, V* lds) {
         const Ctx c = make_ctx(a, t);
-        float2 v[maxv()];
+        V v[maxv()];
         load_first(v, c, a);
+        scale_loaded(v, a);
         stages<0>(lds, v, c, a, a.tw);
     }
     // The same, calling after_loads() once the tile's loads are issued.
     template <class H>
-    __device__ __forceinline__ static void run_tile(const PassArgs& a, int64_t t, float2* lds, H&& after_loads) {
+    __device__ __forceinline__ static void run_tile(const PassArgs& a, int64_t t, V* lds, H&& after_loads) {
         const Ctx c = make_ctx(a, t);
-        float2 v[maxv()];
+        V v[maxv()];
         load_first(v, c, a);
         after_loads();
+        scale_loaded(v, a);
         stages<0>(lds, v, c, a, a.tw);
     }
 
-    __device__ __forceinline__ static void run(const PassArgs& a0, const BatchTable& bt, float2* lds) {
+    __device__ __forceinline__ static void run(const PassArgs& a0, const BatchTable& bt, V* lds) {
         // A merged batch launch first picks its array; both kinds of launch
         // then share one pipeline.
         PassArgs a = a0;
@@ -1101,8 +1220,9 @@ struct PencilPass {
 
 template <int N, int T, int P, bool STRIDED, class IO, int SIGN, int FLAGS = 0, int K = 1, int PLAN = 0>
 __global__ __launch_bounds__(T * P) void pencil_pass_kernel(PassArgs a, BatchTable bt) {
+    using PP = PencilPass<N, T, P, STRIDED, IO, SIGN, FLAGS, K, PLAN>;
     extern __shared__ float2 lds_dyn[];
-    PencilPass<N, T, P, STRIDED, IO, SIGN, FLAGS, K, PLAN>::run(a, bt, lds_dyn);
+    PP::run(a, bt, reinterpret_cast<typename PP::V*>(lds_dyn));
 }
 
 }  // namespace wsfft

@@ -5,7 +5,7 @@
 
 namespace wsfft {
 
-enum StorageKind { kC64 = 0, kF16 = 1, kBF16 = 2 };
+enum StorageKind { kC64 = 0, kF16 = 1, kBF16 = 2, kF16Math = 3 };   // kF16Math: FP16 storage, FP16 arithmetic
 
 struct PassKernel {
     int n;              // pencil length
@@ -38,6 +38,8 @@ WSFFT_DECLARE_FIND(find_pass_f16_neg)
 WSFFT_DECLARE_FIND(find_pass_f16_pos)
 WSFFT_DECLARE_FIND(find_pass_bf16_neg)
 WSFFT_DECLARE_FIND(find_pass_bf16_pos)
+WSFFT_DECLARE_FIND(find_pass_f16m_neg)
+WSFFT_DECLARE_FIND(find_pass_f16m_pos)
 #undef WSFFT_DECLARE_FIND
 // Fused Poisson-solve kernels (complex64; real input and the multiplier with
 // sign -1, real output with sign +1).  NULL when none exists for n.

@@ -16,6 +16,10 @@
 //   (64 for the 4-byte types), and paired (two-element) first-stage loads
 //   where the stage allows them;
 // * non-temporal (streaming) loads and stores help every pass.
+// FP16 storage with FP16 arithmetic (4-byte register and LDS values, argument
+// vb = 4) holds half the state per element: strided tiles of 64 columns
+// (256-byte rows) with twice the elements per thread, exchange rounds of at
+// most ~36 KB, and 256-thread contiguous tiles.
 #pragma once
 #include "fft_device.hpp"
 
@@ -52,8 +56,8 @@ constexpr int cfg_T_contig(int N, int plan = 0) {
 // more bytes in flight) fit per CU within the same FP32 LDS budget.  The
 // 1024-point complex64 tile is one wave as well (two pencils, 17 KB of LDS:
 // 355 us per GiB against 363-390 us for eight pencils in 256 threads).
-constexpr int cfg_P_contig(int N, int plan = 0, int bytes = 8) {
-    const int p = (bytes == 8 && N != 1024 ? 256 : 64) / cfg_T_contig(N, plan);
+constexpr int cfg_P_contig(int N, int plan = 0, int bytes = 8, int vb = 8) {
+    const int p = ((bytes == 8 && N != 1024) || vb == 4 ? 256 : 64) / cfg_T_contig(N, plan);
     return p < 1 ? 1 : p;
 }
 
@@ -70,37 +74,39 @@ constexpr int pow2_floor(int n) {
 // there to stay within registers.
 // Past 512 threads per tile (32 columns x 16 threads) the elements per thread
 // double instead: 1024-thread workgroups are held to 128 VGPRs and spill.
-constexpr int cfg_T_strided(int N, int bytes, int plan = 0) {
+constexpr int cfg_T_strided(int N, int bytes, int plan = 0, int vb = 8) {
     (void)bytes;
     int e = is_pow2(N) ? (N <= 128 ? 16 : 32) : 24;
     if ((N + e - 1) / e > 16) e *= 2;
+    if (vb == 4 && is_pow2(N) && N <= 512) e *= 2;   // longer or radix-3 pencils would spill
     int t = (N + e - 1) / e;
     const int tmax = N / max_radix(make_radices(N, plan));
     if (tmax >= 1 && t > tmax) t = tmax;
     return t < 1 ? 1 : t;
 }
-constexpr int cfg_P_strided(int N, int bytes, int plan = 0) {
+constexpr int cfg_P_strided(int N, int bytes, int plan = 0, int vb = 8) {
     (void)bytes;
     int p = 32;
-    if (N <= 64) p = 64;                   // one full wave of columns at least
-    const int cap = pow2_floor(1024 / cfg_T_strided(N, bytes, plan));
+    if (N <= 64 || (vb == 4 && is_pow2(N))) p = 64;   // one full wave of columns at least
+    const int cap = pow2_floor(1024 / cfg_T_strided(N, bytes, plan, vb));
     return p > cap ? cap : p;
 }
 // Smallest K dividing N whose exchange round fits the LDS budget (twice the
 // per-round budget for workgroups of up to 512 threads, two of which still
 // fit per CU; four times at 1024 points); when that takes more than 8
 // rounds, accept up to twice the budget instead.
-constexpr int cfg_K_strided(int N, int bytes, int plan = 0) {
-    const int p = cfg_P_strided(N, bytes, plan);
+constexpr int cfg_K_strided(int N, int bytes, int plan = 0, int vb = 8) {
+    const int p = cfg_P_strided(N, bytes, plan, vb);
     // 1024-point tiles run best with two rounds and one workgroup per CU
-    const int budget = N >= 1024 ? 4 * kLdsRoundBudget
+    const int budget = vb == 4 ? kLdsRoundBudget
+                       : N >= 1024 ? 4 * kLdsRoundBudget
                        : cfg_T_strided(N, bytes, plan) * p <= 512 ? 2 * kLdsRoundBudget : kLdsRoundBudget;
     int first = 0;
     for (int k = 1; k <= N && !first; ++k)
-        if (N % k == 0 && (N / k) * (p + 1) * 8 <= budget) first = k;
+        if (N % k == 0 && (N / k) * (p + 1) * vb <= budget) first = k;
     if (first && first <= 8) return first;
     for (int k = 1; k <= N; ++k)
-        if (N % k == 0 && (N / k) * (p + 1) * 8 <= 2 * kLdsRoundBudget) return k;
+        if (N % k == 0 && (N / k) * (p + 1) * vb <= 2 * kLdsRoundBudget) return k;
     return first ? first : N;
 }
 

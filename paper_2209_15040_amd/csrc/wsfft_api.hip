@@ -57,6 +57,7 @@ struct Pass {
     int four_step;                // 0 direct, 1 pass A, 2 pass B
     int64_t tw_off, tw4_off;      // element offsets into the twiddle block (tw4: -1 none)
     float pass_scale;             // 2^-s_p
+    float inv_scale;              // the pass's scale in wsfft_execute_inverse
     int outer_dim;                // count whose stride spans whole arrays: 0 = C, 1 = O1, 2 = O2
     int variant;                  // kernel launch variant (autotuner)
     dim3 grid;
@@ -129,8 +130,10 @@ void root_fp64(int64_t m, int64_t n, double* re, double* im) {
     *im = -sr;   // forward kernel exp(-i*angle)
 }
 
-StorageKind kind_of(wsfft_dtype_t d) {
-    return d == WSFFT_C64 ? kC64 : (d == WSFFT_C16_FP16 ? kF16 : kBF16);
+StorageKind kind_of(wsfft_dtype_t d, unsigned flags) {
+    if (d == WSFFT_C64) return kC64;
+    if (d == WSFFT_C16_BF16) return kBF16;
+    return (flags & WSFFT_FLAG_FP16_MATH) ? kF16Math : kF16;
 }
 
 int elem_bytes(wsfft_dtype_t d) { return d == WSFFT_C64 ? 8 : 4; }
@@ -239,14 +242,15 @@ int64_t blocks_for(const Pass& P, const PassKernel* k) {
     return (a.C + k->per_block - 1) / k->per_block;
 }
 
-const char* kind_name(wsfft_dtype_t d) {
+const char* kind_name(wsfft_dtype_t d, unsigned flags) {
+    if (d == WSFFT_C16_FP16 && (flags & WSFFT_FLAG_FP16_MATH)) return "c16-fp16-math";
     return d == WSFFT_C64 ? "c64" : (d == WSFFT_C16_FP16 ? "c16-fp16" : "c16-bf16");
 }
 
 void describe_plan(wsfft_plan_s* plan) {
     char buf[256];
     std::snprintf(buf, sizeof buf, "%lldx%lldx%lld %s sign=%d S=%d:", (long long)plan->n[0], (long long)plan->n[1],
-                  (long long)plan->n[2], kind_name(plan->dtype), plan->sign, plan->scale_log2);
+                  (long long)plan->n[2], kind_name(plan->dtype, plan->flags), plan->sign, plan->scale_log2);
     plan->desc = buf;
     for (const Pass& P : plan->passes) {
         std::snprintf(buf, sizeof buf, " %c%s[%s n=%lld v%d wg=%d per=%d lds=%d grid=%u]", "xyz"[P.axis],
@@ -302,7 +306,7 @@ std::string tune_key(const wsfft_plan_s* plan, const Pass& P, const char* arch) 
     const PassArgs& a = P.args;
     char buf[320];
     std::snprintf(buf, sizeof buf, "%s|%s|s%d|n%lld|st%d|fs%d|C%lld|O%lld,%lld|es%lld|os%lld,%lld", arch,
-                  kind_name(plan->dtype), plan->sign, (long long)P.n, (int)P.strided, P.four_step,
+                  kind_name(plan->dtype, plan->flags), plan->sign, (long long)P.n, (int)P.strided, P.four_step,
                   (long long)a.C, (long long)a.O1, (long long)a.O2, (long long)a.es_in, (long long)a.os1_in,
                   (long long)a.os2_in);
     return buf;
@@ -314,7 +318,7 @@ void set_stage_tw(const wsfft_plan_s* plan, Pass& P) {
 }
 
 bool use_variant(wsfft_plan_s* plan, Pass& P, int v) {
-    const StorageKind kind = kind_of(plan->dtype);
+    const StorageKind kind = kind_of(plan->dtype, plan->flags);
     const PassKernel* kn = find_pass_kernel(kind, -1, (int)P.n, P.strided, P.four_step == 1, v);
     const PassKernel* kp = find_pass_kernel(kind, +1, (int)P.n, P.strided, P.four_step == 1, v);
     if (!kn || !kp || kn->prepare() != hipSuccess || kp->prepare() != hipSuccess) return false;
@@ -386,7 +390,7 @@ void tune_plan(wsfft_plan_s* plan, bool requested) {
     hipStream_t st = nullptr;
     const int64_t bytes = plan->n[0] * plan->n[1] * plan->n[2] * elem_bytes(plan->dtype);
     for (Pass& P : plan->passes) {
-        const StorageKind kind = kind_of(plan->dtype);
+        const StorageKind kind = kind_of(plan->dtype, plan->flags);
         int nvar = 0;
         for (int v = 0; v < kMaxVariants; ++v)
             if (find_pass_kernel(kind, plan->sign, (int)P.n, P.strided, P.four_step == 1, v)) ++nvar;
@@ -461,7 +465,8 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     if (sign != 1 && sign != -1) return fail(WSFFT_ERROR_INVALID_VALUE);
     if (dtype != WSFFT_C64 && dtype != WSFFT_C16_FP16 && dtype != WSFFT_C16_BF16)
         return fail(WSFFT_ERROR_INVALID_VALUE);
-    if (flags & ~(WSFFT_FLAG_FP32_TWIDDLES | WSFFT_FLAG_TUNE)) return fail(WSFFT_ERROR_INVALID_VALUE);
+    if (flags & ~(WSFFT_FLAG_FP32_TWIDDLES | WSFFT_FLAG_TUNE | WSFFT_FLAG_FP16_MATH)) return fail(WSFFT_ERROR_INVALID_VALUE);
+    if ((flags & WSFFT_FLAG_FP16_MATH) && dtype != WSFFT_C16_FP16) return fail(WSFFT_ERROR_INVALID_VALUE);
     const int64_t dims[3] = {nx, ny, nz};
     for (int64_t d : dims)
         if (d > WSFFT_MAX_AXIS || !is_smooth23(d)) return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
@@ -508,7 +513,7 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
         return tables.back().off;
     };
 
-    const StorageKind kind = kind_of(dtype);
+    const StorageKind kind = kind_of(dtype, flags);
     int S = 0;
     for (const AxisGeo& g : order) {
         const bool is_split = !direct_ok(g.n, g.inner != 1);
@@ -541,6 +546,16 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
         }
     }
     plan->scale_log2 = S;
+    // wsfft_execute_inverse: complex64 plans fold 1/N into the last pass; the
+    // 16-bit plans scale pass p by 2^s_p / n_p, about 1/sqrt(n_p) like the
+    // forward 2^-s_p, so the inverse is 2^S/N times the opposite-sign sum
+    // (the exact inverse of wsfft_execute) and stays within the FP16 range
+    {
+        const double N = (double)nx * (double)ny * (double)nz;
+        for (Pass& P : plan->passes)
+            P.inv_scale = half ? (float)(1.0 / ((double)P.pass_scale * (double)P.n)) : P.pass_scale;
+        if (!half && !plan->passes.empty()) plan->passes.back().inv_scale = (float)((double)plan->passes.back().pass_scale / N);
+    }
 
     // kernels
     for (Pass& P : plan->passes) {
@@ -725,11 +740,7 @@ bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out,
     const bool ip = in == out;
     a.src = sel(ip ? P.src_sel_ip : P.src_sel);
     a.dst = sel(ip ? P.dst_sel_ip : P.dst_sel);
-    a.scale = P.pass_scale;
-    if (mode == 2 && pi + 1 == plan->passes.size()) {
-        const double N = (double)plan->n[0] * (double)plan->n[1] * (double)plan->n[2];
-        a.scale = (float)((double)P.pass_scale / N);
-    }
+    a.scale = mode == 2 ? P.inv_scale : P.pass_scale;
     const int sign = mode == 0 ? plan->sign : -plan->sign;
     const PassKernel* k = sign < 0 ? P.kern_neg : P.kern_pos;
     return k->launch(a, nullptr, grid, stream) == hipSuccess;
@@ -793,9 +804,7 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
                 d.O1 = P.args.O1;
                 d.es = P.args.es_in;
                 d.os1 = P.args.os1_in;
-                d.scale = P.pass_scale;
-                if (mode == 2 && pi + 1 == p->passes.size())
-                    d.scale = (float)((double)P.pass_scale / ((double)p->n[0] * (double)p->n[1] * (double)p->n[2]));
+                d.scale = mode == 2 ? P.inv_scale : P.pass_scale;
                 tiles += blocks_for(P, g.k);
                 d.tile_end = tiles;
                 if (e == c0) shared = P.args;
@@ -942,6 +951,8 @@ const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strid
             return sign < 0 ? find_pass_f16_neg(n, strided, four_step, v) : find_pass_f16_pos(n, strided, four_step, v);
         case kBF16:
             return sign < 0 ? find_pass_bf16_neg(n, strided, four_step, v) : find_pass_bf16_pos(n, strided, four_step, v);
+        case kF16Math:
+            return sign < 0 ? find_pass_f16m_neg(n, strided, four_step, v) : find_pass_f16m_pos(n, strided, four_step, v);
     }
     return nullptr;
 }

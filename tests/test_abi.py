@@ -83,6 +83,12 @@ def test_unknown_flag_rejected(lib):
     assert lib.wsfft_get_last_error() == INVALID
 
 
+@pytest.mark.parametrize("dtype", [0, 2])
+def test_fp16_math_flag_only_for_fp16_storage(lib, dtype):
+    assert lib.wsfft_plan_create_ex(8, 8, 8, dtype, -1, 4) is None   # WSFFT_FLAG_FP16_MATH
+    assert lib.wsfft_get_last_error() == INVALID
+
+
 def test_valid_plan_without_device_reports_no_device(lib):
     import torch
     if torch.cuda.is_available():
