@@ -12,9 +12,12 @@
 // * 32 elements per thread, the exchange split into rounds of up to ~72 KB
 //   of LDS, so two workgroups stay resident per CU and one's transform and
 //   store drain overlap the other's loads;
-// * contiguous pencils: 16 elements per thread, 256-thread workgroups
-//   (64 for the 4-byte types), and paired (two-element) first-stage loads
-//   where the stage allows them;
+// * contiguous pencils: N/16 threads each where the widest stage leaves
+//   every thread a butterfly (512 points: 16 threads x 32 elements, radix
+//   32 x 16, for complex64; 32 threads x 16 elements, radix 8 x 8 x 8, for
+//   the 4-byte types), 256-thread workgroups (one wave for the 4-byte types
+//   and for 1024-point complex64), and paired (two-element) first-stage
+//   loads where the stage allows them;
 // * non-temporal (streaming) loads and stores help every pass.
 // FP16 storage with FP16 arithmetic (4-byte register and LDS values, argument
 // vb = 4) holds half the state per element: strided tiles of 64 columns
@@ -31,9 +34,10 @@ constexpr int kPassFlags = kFlagNontemporal;
 
 // Radix plan of the default contiguous kernel: the fewest stages, except
 // that pencils of up to 32 points take radix <= 8 stages so that 4 threads
-// share a pencil (cfg_T_contig), and FP16 arithmetic takes radix <= 16
-// stages (512 points: 185 us against 197 us for 16 x 32).
-constexpr int cfg_plan_contig(int N, int vb = 8) { return N <= 32 ? 2 : (vb == 4 ? 1 : 0); }
+// share a pencil (cfg_T_contig), and the 4-byte storage types take radix
+// <= 16 stages (512 points: 8 x 8 x 8 with 16 elements per thread, 185-188
+// us per GiB against 197-208 us for 16 x 32).
+constexpr int cfg_plan_contig(int N, int bytes = 8) { return N <= 32 ? 2 : (bytes == 4 ? 1 : 0); }
 
 // Radix plan of the default strided kernel (see make_radices).
 constexpr int cfg_plan_strided(int N, int bytes) {
