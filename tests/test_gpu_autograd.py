@@ -121,6 +121,36 @@ def test_poisson_directional_fd(ws):
         assert abs(fd - an) <= 1e-3 * abs(an) + 1e-6
 
 
+def test_poisson_256_directional_fd_h1e3(ws):
+    """The workload's own check: central differences with h = 1e-3 on the
+    256^3 grid (64 bumps, seed 4) along four smooth bump-field directions,
+    the loss accumulated in FP64 on the host, against <grad, v> from the
+    backward pass.  The loss is linear in f, so the difference has no
+    truncation error; what remains is FP32 rounding of f +- h v and of u."""
+    n = 256
+    f, w = _poisson_inputs(n, 4)
+    ft = torch.from_numpy(f.astype(np.float32)).cuda()
+    w32 = w.astype(np.float32)
+    wt = torch.from_numpy(w32).cuda()
+    fg = ft.clone().requires_grad_(True)
+    (ws.poisson_solve(fg) * wt).sum().backward()
+    g = to_host(fg.grad).astype(np.float64)
+
+    def L(x):
+        return float(np.sum(to_host(ws.poisson_solve(x)).astype(np.float64) * w32))
+
+    h = 1e-3
+    for s in range(4):
+        v = synth.gaussian_bumps(n, 8, 0.1, seed=300 + s)
+        v /= np.abs(v).max()
+        v32 = v.astype(np.float32)
+        vt = torch.from_numpy(v32).cuda()
+        fd = (L(ft + h * vt) - L(ft - h * vt)) / (2 * h)
+        an = float(np.sum(g * v32))
+        print(f"256^3 h=1e-3 direction {s}: fd {fd:.6e} analytic {an:.6e} rel {abs(fd - an) / abs(an):.2e}")
+        assert abs(fd - an) <= 1e-3 * abs(an)
+
+
 def test_poisson_per_coordinate_fd_small(ws):
     n = 16
     f, w = _poisson_inputs(n, 12)
