@@ -312,6 +312,10 @@ def cpu_baseline():
                       f"(forward {fwd_s / reps:.2f} s); cpu: {cpu}"}
 
 
+VARIANTS = ["fp16", "bf16", "bf16_fp32_twiddles", "fp16_math", "batched_96", "2d_8192", "1d_65536_x1024",
+            "32cubed", "1024cubed", "poisson_256"]
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,9 +323,15 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variants", default="", help="comma-separated subset of the variants (default: all)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for rocprofv3 --pmc runs)")
     args = ap.parse_args()
+    only = [v for v in args.variants.split(",") if v] if args.variants else list(VARIANTS)
+    unknown = [v for v in only if v not in VARIANTS]
+    if unknown:
+        print(f"unknown variants {unknown}; known: {VARIANTS}", file=sys.stderr)
+        return 2
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -360,16 +370,21 @@ def main() -> int:
     variants = {}
     if not args.no_variants:
         vs = max(5, K // 2)
-        variants["fp16"] = variant_c16(ws, torch, "fp16", vs, 2)
-        variants["bf16"] = variant_c16(ws, torch, "bf16", vs, 2)
-        variants["bf16_fp32_twiddles"] = variant_c16(ws, torch, "bf16", vs, 2, ws.FLAG_FP32_TWIDDLES)
-        variants["fp16_math"] = variant_c16(ws, torch, "fp16", vs, 2, ws.FLAG_FP16_MATH)
-        variants["batched_96"] = variant_batched(ws, torch, vs, 2)
-        variants["2d_8192"] = variant_rank(ws, torch, (8192, 8192, 1), vs, 2)
-        variants["1d_65536_x1024"] = variant_rank(ws, torch, (65536, 1, 1), vs, 2, batch=1024)
-        variants["32cubed"] = variant_rank(ws, torch, (32, 32, 32), vs, 2, one_launch=True)
-        variants["1024cubed"] = variant_cube1024(ws, torch, vs, 2)
-        variants["poisson_256"] = variant_poisson(ws, torch, vs, 2)
+        runs = {
+            "fp16": lambda: variant_c16(ws, torch, "fp16", vs, 2),
+            "bf16": lambda: variant_c16(ws, torch, "bf16", vs, 2),
+            "bf16_fp32_twiddles": lambda: variant_c16(ws, torch, "bf16", vs, 2, ws.FLAG_FP32_TWIDDLES),
+            "fp16_math": lambda: variant_c16(ws, torch, "fp16", vs, 2, ws.FLAG_FP16_MATH),
+            "batched_96": lambda: variant_batched(ws, torch, vs, 2),
+            "2d_8192": lambda: variant_rank(ws, torch, (8192, 8192, 1), vs, 2),
+            "1d_65536_x1024": lambda: variant_rank(ws, torch, (65536, 1, 1), vs, 2, batch=1024),
+            "32cubed": lambda: variant_rank(ws, torch, (32, 32, 32), vs, 2, one_launch=True),
+            "1024cubed": lambda: variant_cube1024(ws, torch, vs, 2),
+            "poisson_256": lambda: variant_poisson(ws, torch, vs, 2),
+        }
+        assert list(runs) == VARIANTS
+        for name in only:
+            variants[name] = runs[name]()
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle, 512^3 round trip")
