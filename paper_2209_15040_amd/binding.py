@@ -115,7 +115,11 @@ def shape_xyz(shape, dtype: int):
 
 
 class Plan:
-    """A wsfft plan for an nx x ny x nz transform (``wsfft_plan_create_ex``)."""
+    """A wsfft plan for an nx x ny x nz transform (``wsfft_plan_create_ex``).
+
+    ``dtype``: "c64", "fp16" or "bf16" (16-bit tensors carry a trailing
+    (re, im) axis).  ``flags``: FLAG_FP32_TWIDDLES, FLAG_TUNE and, for "fp16",
+    FLAG_FP16_MATH (packed FP16 butterflies instead of FP32 arithmetic)."""
 
     def __init__(self, nx: int, ny: int = 1, nz: int = 1, dtype="c64", sign: int = -1, flags: int = 0):
         self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
