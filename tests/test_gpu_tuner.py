@@ -32,12 +32,13 @@ def test_forced_variants_match_oracle(ws, shape, variant, monkeypatch):
     assert rel_l2(r, a) <= 2e-6
 
 
+@pytest.mark.parametrize("flags", [0, 4], ids=["fp32-math", "fp16-math"])   # 4: WSFFT_FLAG_FP16_MATH
 @pytest.mark.parametrize("variant", [0, 1, 2])
-def test_forced_variants_fp16(ws, variant, monkeypatch):
+def test_forced_variants_fp16(ws, variant, flags, monkeypatch):
     monkeypatch.setenv("WSFFT_TUNE_FORCE", str(variant))
     nx, ny, nz = 512, 256, 16
     pairs = synth.to_fp16_pairs(synth.normal_c((nz, ny, nx), seed=32, scale=0.5))
-    p = ws.Plan(nx, ny, nz, "fp16", -1)
+    p = ws.Plan(nx, ny, nz, "fp16", -1, flags)
     got = c16_to_c128(p.execute(c16_to_dev(pairs, "fp16")), "fp16") * 2.0 ** p.scale_log2
     want = oracle.fftn(synth.pairs_to_c128(pairs, "fp16"), -1)
     assert rel_l2(got, want) <= 3e-3
