@@ -298,6 +298,13 @@ def cpu_baseline():
         total += t2 - t0
         reps += 1
     secs = total / (2 * reps)
+    # the same oracle on one core: one 256^3 forward transform (a 512^3 one
+    # takes most of a minute there)
+    n1 = 256
+    a1 = np.ascontiguousarray(a[:n1, :n1, :n1])
+    t0 = time.perf_counter()
+    oracle.fftn(a1, -1, 1)
+    one_core_s = time.perf_counter() - t0
     cpu = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -309,7 +316,10 @@ def cpu_baseline():
     return {"value": flops(N) / secs / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} x the 512^3 forward+inverse round trip (the headline step), FP64 C oracle, "
                       f"{threads} threads, {total:.1f} s in all; {secs * 1e3:.0f} ms per transform "
-                      f"(forward {fwd_s / reps:.2f} s); cpu: {cpu}"}
+                      f"(forward {fwd_s / reps:.2f} s); cpu: {cpu}",
+            "one_core": {"value": flops(n1 ** 3) / one_core_s / 1e9, "unit": "GFLOP/s", "cores": 1,
+                         "sample": f"one 256^3 forward transform (a corner of the same input), 1 thread, "
+                                   f"{one_core_s:.1f} s"}}
 
 
 VARIANTS = ["fp16", "bf16", "bf16_fp32_twiddles", "fp16_math", "batched_96", "2d_8192", "1d_65536_x1024",
