@@ -318,7 +318,7 @@ def fftn(x: torch.Tensor, sign: int = -1) -> torch.Tensor:
 
 
 def ifftn(x: torch.Tensor) -> torch.Tensor:
-    """Normalised inverse of :func:`fftn` (1/N and the opposite sign)."""
+    """The inverse of :func:`fftn`: the opposite sign times 2^S/N (S = 0 for complex64)."""
     return get_plan(x, -1).execute_inverse(x)
 
 
@@ -339,7 +339,8 @@ class FFTn(torch.autograd.Function):
 
 
 class IFFTn(torch.autograd.Function):
-    """y = (1/N) DFT with kernel sign -sign; backward = (1/N) DFT with sign `sign`."""
+    """y = 2^S/N DFT with kernel sign -sign (S = 0 for complex64); backward = 2^S/N DFT
+    with sign `sign`."""
 
     @staticmethod
     def forward(ctx, x, sign: int = -1):
