@@ -177,11 +177,18 @@ def variant_batched(ws, torch, steps, warmup):
     timed_out = bp.timed_out()
     tiles = bp.tiles
     bp.close()
+    # the same batch with autotuned plans (each pass's launch variant timed at
+    # creation; the choices go to this process's tuning cache)
+    tuned = [ws.Plan(nx, ny, nz, "c64", -1, ws.FLAG_TUNE) for nx, ny, nz in shapes]
+    ms_tuned, _ = time_events(lambda: ws.execute_batched(tuned, xs, ys), steps, warmup)
+    n_tuned = sum(d.count(" v1 ") + d.count(" v2 ") for d in (p.describe() for p in tuned))
+    del tuned
     byts = sum(2 * 8 * nx * ny * nz * sum(d > 1 for d in (nx, ny, nz)) for nx, ny, nz in shapes)
     del xs, ys
     torch.cuda.empty_cache()
     return {"arrays": len(shapes), "elements": tot, "GiB_in_plus_out": 2 * 8 * tot / 2 ** 30,
-            "ms_batched": ms, "ms_loop_of_plans": ms_loop, "ms_one_persistent_launch": ms_persist,
+            "ms_batched": ms, "ms_batched_tuned": ms_tuned, "tuned_passes_off_default": n_tuned,
+            "ms_loop_of_plans": ms_loop, "ms_one_persistent_launch": ms_persist,
             "persistent_tiles": tiles, "persistent_timed_out": timed_out,
             "GFLOPs": fl / (min(ms, ms_persist) * 1e-3) / 1e9,
             "hbm_frac": byts / (min(ms, ms_persist) * 1e-3) / HBM_PEAK}
@@ -346,6 +353,10 @@ def main() -> int:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
+    # a tuning cache of this run only: plans without WSFFT_FLAG_TUNE take the
+    # default variants whatever earlier runs recorded
+    import tempfile
+    os.environ["WSFFT_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="wsfft_tune_"), "cache.txt")
     import torch
     from paper_2209_15040_amd import binding as ws
     if not torch.cuda.is_available():
