@@ -19,8 +19,9 @@
  *   WSFFT_C64       FP32 re, FP32 im (8 bytes, 8-byte aligned)
  *   WSFFT_C16_FP16  FP16 re, FP16 im (4 bytes, 4-byte aligned)
  *   WSFFT_C16_BF16  BF16 re, BF16 im (4 bytes, 4-byte aligned)
- * All arithmetic is FP32 (the paper measures FP32 and FP16; Section 4.1 and
- * Section 5).  Twiddle factors are evaluated in FP64 on the host and rounded
+ * Arithmetic is FP32 (the paper measures FP32 and FP16; Section 4.1 and
+ * Section 5), or packed FP16 for WSFFT_C16_FP16 plans created with
+ * WSFFT_FLAG_FP16_MATH.  Twiddle factors are evaluated in FP64 on the host and rounded
  * to nearest even: to the storage type for the 16-bit types, to FP32 for
  * WSFFT_C64 or when WSFFT_FLAG_FP32_TWIDDLES is given.
  *
