@@ -11,10 +11,11 @@ shape ``(nz, ny, nx)`` (x fastest), i.e. element (x, y, z) at linear index
 here normalises unless its name says so.
 
 The arithmetic lives in ``wsfft_oracle.c`` (plain C, FP64, recursive
-mixed-radix Cooley-Tukey, pthreads over pencils).  ``poisson_*`` below follow
-the spectral Poisson operator u = IFFT(-FFT(f)/|k|^2), k = 0 mode zeroed,
-which the differentiable-solve workload defines.  Parity status: pinned (see
-``tests/test_oracle.py``).
+mixed-radix Cooley-Tukey, pthreads over pencils).  ``rfftn`` / ``irfftn``
+define the half-spectrum forms of the same DFT for real input and output.
+``poisson_*`` below follow the spectral Poisson operator
+u = IFFT(-FFT(f)/|k|^2), k = 0 mode zeroed, which the differentiable-solve
+workload defines.  Parity status: pinned (see ``tests/test_oracle.py``).
 """
 from __future__ import annotations
 
@@ -112,6 +113,58 @@ def fft1d_batch(a, sign: int = -1, threads: int | None = None) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"oracle_fft1d_batch failed with {rc}")
     return out
+
+
+# --- real input and real output ------------------------------------------------
+# The transform of Section 1 applied to a real array: its DFT is Hermitian,
+# X[-k] = conj(X[k]), so the bins kx = 0 .. nx//2 along x determine all the
+# others.  The paper transforms complex data only (Section 5); these two
+# functions define the half-spectrum forms by the full DFT above.
+
+def rfftn(a, threads: int | None = None) -> np.ndarray:
+    """Forward (sign -1) DFT of a real array of shape (nz, ny, nx) (or lower
+    rank, trailing axes as in :func:`fftn`), kept for kx = 0 .. nx//2:
+    shape (..., nx//2 + 1), unnormalised.  Definition: the full complex DFT
+    of the real input, sliced."""
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        raise TypeError("rfftn takes a real array")
+    X = fftn(a.astype(np.complex128), -1, threads)
+    return np.ascontiguousarray(X[..., : a.shape[-1] // 2 + 1])
+
+
+def _dft_along(a: np.ndarray, axis: int, sign: int, threads) -> np.ndarray:
+    """Unnormalised 1D DFTs along one axis of a complex array."""
+    m = np.ascontiguousarray(np.moveaxis(a, axis, -1))
+    out = fft1d_batch(m.reshape(-1, m.shape[-1]), sign, threads).reshape(m.shape)
+    return np.moveaxis(out, -1, axis)
+
+
+def irfftn(H, nx: int, threads: int | None = None) -> np.ndarray:
+    """Unnormalised complex-to-real transform (sign +1) of a half spectrum
+    H of shape (..., nx//2 + 1) to a real array of shape (..., nx).
+
+    Definition, one axis at a time: sign +1 DFTs along every axis but x (of
+    the half spectrum as given); then along x the Hermitian extension
+    Y[k] for 0 < k < nx/2, conj(Y[nx - k]) for k > nx/2, and the real parts
+    of Y[0] and (nx even) Y[nx/2], whose imaginary parts a Hermitian
+    spectrum does not have; its sign +1 DFT is real.  For the half spectrum
+    of a real array a, irfftn(rfftn(a), nx) = N * a."""
+    H = np.asarray(H, dtype=np.complex128)
+    nh = nx // 2 + 1
+    if H.shape[-1] != nh:
+        raise ValueError(f"half spectrum of {nx} points has {nh} bins, got {H.shape[-1]}")
+    Y = H
+    for axis in range(H.ndim - 1):
+        Y = _dft_along(Y, axis, +1, threads)
+    ext = np.empty(H.shape[:-1] + (nx,), dtype=np.complex128)
+    ext[..., :nh] = Y
+    ext[..., 0] = Y[..., 0].real
+    if nx % 2 == 0:
+        ext[..., nx // 2] = Y[..., nx // 2].real
+    k = np.arange(nh, nx)
+    ext[..., k] = np.conj(Y[..., nx - k])
+    return _dft_along(ext, H.ndim - 1, +1, threads).real
 
 
 # --- spectral Poisson operator ------------------------------------------------

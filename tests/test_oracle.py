@@ -293,3 +293,92 @@ def test_poisson_self_adjoint():
     lhs = np.sum(oracle.poisson_apply(a) * b)
     rhs = np.sum(a * oracle.poisson_apply(b))
     assert abs(lhs - rhs) < 1e-13 * np.sqrt(np.sum(a * a) * np.sum(b * b))
+
+
+# --- real input, half spectrum (rfftn) and its complex-to-real inverse (irfftn) ---
+
+RSHAPES = [(1, 1, 2), (1, 1, 7), (1, 1, 8), (3, 4, 6), (2, 5, 9), (4, 3, 12), (6, 2, 16)]   # (nz, ny, nx)
+
+
+@pytest.mark.parametrize("shape", RSHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_rfftn_brute_force(shape):
+    """The half spectrum is bins kx = 0 .. nx//2 of the directly summed DFT."""
+    a = synth.normal_c(shape, seed=sum(shape)).real
+    want = brute_force_dft(a.astype(np.complex128), -1)[..., : shape[-1] // 2 + 1]
+    got = oracle.rfftn(a)
+    assert got.shape == want.shape
+    assert rel_l2(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (3, 5, 9), (1, 1, 16)], ids=lambda s: "x".join(map(str, s)))
+def test_rfftn_hermitian_reconstruction(shape):
+    """The full DFT of a real array is recovered from the half spectrum by
+    X[kx, ky, kz] = conj(X[-kx, -ky, -kz])."""
+    nz, ny, nx = shape
+    a = synth.uniform_c(shape, seed=7 * nx).real
+    H = oracle.rfftn(a)
+    full = np.empty(shape, np.complex128)
+    nh = nx // 2 + 1
+    full[..., :nh] = H
+    for kx in range(nh, nx):
+        # -k taken modulo each axis length
+        full[..., kx] = np.conj(H[(-np.arange(nz)) % nz][:, (-np.arange(ny)) % ny][..., nx - kx])
+    assert rel_l2(full, brute_force_dft(a.astype(np.complex128), -1)) < 1e-13
+
+
+@pytest.mark.parametrize("nx,m", [(16, 0), (16, 3), (16, 8), (12, 5), (9, 4)])
+def test_rfftn_cosine(nx, m):
+    """cos(2*pi*m*x/nx) has N/2 in bin m (N at m = 0 and m = nx/2) and 0 elsewhere."""
+    ny, nz = 3, 2
+    x = np.arange(nx)
+    a = np.broadcast_to(np.cos(2 * np.pi * m * x / nx), (nz, ny, nx))
+    H = oracle.rfftn(np.ascontiguousarray(a))
+    want = np.zeros((nz, ny, nx // 2 + 1), np.complex128)
+    N = nx * ny * nz
+    want[0, 0, m] = N if (m == 0 or 2 * m == nx) else N / 2
+    assert np.max(np.abs(H - want)) < 1e-12 * N
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (3, 5, 9), (2, 2, 2), (1, 1, 16), (8, 4, 12)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_irfftn_round_trip(shape):
+    """irfftn(rfftn(a)) = N * a for real a."""
+    a = synth.normal_c(shape, seed=3 * sum(shape)).real
+    back = oracle.irfftn(oracle.rfftn(a), shape[-1])
+    assert back.dtype == np.float64 and back.shape == a.shape
+    assert rel_l2(back, a.size * a) < 1e-13
+
+
+@pytest.mark.parametrize("nx", [8, 9, 12])
+def test_irfftn_single_bin_closed_forms(nx):
+    """One nonzero bin c at (kx, ky, kz) = (m, q, 0): the output is
+    2 Re(c exp(2*pi*i*(m x/nx + q y/ny))) for 0 < m < nx/2; at m = 0 and
+    m = nx/2 only Re(c) counts: Re(c) exp-free in x (or (-1)^x) times
+    Re(exp(2*pi*i*q y/ny)).  Fixes the sign along y and x and the
+    discarded imaginary parts."""
+    ny, nz = 5, 3
+    nh = nx // 2 + 1
+    x = np.arange(nx)[None, None, :]
+    y = np.arange(ny)[None, :, None]
+    c = 0.75 - 1.25j
+    for m in range(nh):
+        for q in (0, 2):
+            H = np.zeros((nz, ny, nh), np.complex128)
+            H[0, q, m] = c
+            got = oracle.irfftn(H, nx)
+            ph = np.exp(2j * np.pi * q * y / ny)
+            if m == 0 or 2 * m == nx:
+                # the x step keeps the real part of the y-transformed bin
+                want = np.broadcast_to((c * ph).real * np.cos(np.pi * 2 * m * x / nx), (nz, ny, nx))
+            else:
+                want = np.broadcast_to(2 * (c * ph * np.exp(2j * np.pi * m * x / nx)).real, (nz, ny, nx))
+            assert np.max(np.abs(got - want)) < 1e-12, (m, q)
+
+
+def test_real_forms_numpy_cross_check():
+    """NumPy's real transforms as a secondary check (never the oracle)."""
+    a = synth.normal_c((12, 16, 18), seed=91).real
+    H = oracle.rfftn(a)
+    assert rel_l2(H, np.fft.rfftn(a)) < 1e-12
+    Hr = synth.normal_c(H.shape, seed=92)
+    assert rel_l2(oracle.irfftn(Hr, 18), np.fft.irfftn(Hr, s=a.shape, axes=(0, 1, 2)) * a.size) < 1e-12
