@@ -42,12 +42,20 @@
  * stream work completes.  A plan owns its twiddle tables and, for axes longer
  * than one pass can hold, its work buffer.  Plans are immutable after
  * creation, so one plan may run concurrently on several streams -- except
- * plans with a work buffer (wsfft_plan_work_bytes > 0), which must not run
- * concurrently with themselves.  `in == out` is allowed, except for a plan
- * with exactly one split axis (wsfft_plan_num_passes larger than the number
- * of axes of length > 1 and wsfft_plan_work_bytes == 0), whose first pass must
- * read a buffer it does not write: such calls return WSFFT_ERROR_INVALID_VALUE.
- * Otherwise `in` and `out` must not overlap, and `in` is never written.
+ * calls that use the plan's work buffer (below), which must not run
+ * concurrently with each other.  `in == out` (in place) is allowed for every
+ * plan.  Otherwise `in` and `out` must not overlap, and `in` is never written.
+ *
+ * Work buffer: an axis longer than one pass holds is split into two passes
+ * (four-step, paper Section 8), and the first of them cannot write the
+ * positions it reads.  A plan with such an axis therefore owns a work buffer
+ * of one array (wsfft_plan_work_bytes), allocated at creation; calls go
+ * through it when the plan has two split axes, or when it has one and the
+ * call is in place.
+ *
+ * Logging: with the environment variable WSFFT_LOG=1 every plan creation
+ * prints the plan's pass schedule (axis, layout, length, kernel variant,
+ * workgroup size, tile width, LDS bytes, grid) to stderr.
  */
 #ifndef WSFFT_H
 #define WSFFT_H
@@ -94,15 +102,17 @@ typedef enum {
 
 /*
  * Autotuning.  Passes of the hot lengths (powers of two up to 1024 strided,
- * 4096 contiguous) have several compiled launch variants (radix schedule,
- * tile width).  Plan creation picks, per pass geometry, the variant recorded
- * in the tuning cache ($WSFFT_TUNE_CACHE, else $HOME/.cache/wsfft_tune.txt);
- * with WSFFT_FLAG_TUNE or the environment WSFFT_TUNE=1 it times every
+ * 16384 contiguous) have several compiled launch variants (radix schedule,
+ * tile width).  With WSFFT_FLAG_TUNE or the environment WSFFT_TUNE=1, plan
+ * creation picks, per pass geometry, the variant recorded in the tuning cache
+ * ($WSFFT_TUNE_CACHE, else $HOME/.cache/wsfft_tune.txt), or times every
  * variant of uncached geometries with HIP events on two temporary device
  * buffers of one array each (allocated and freed inside plan creation) and
- * appends the winner to the cache.  WSFFT_TUNE=0 disables both, and the
- * diagnostic WSFFT_TUNE_FORCE=<v> selects variant v wherever it exists.
- * Execution is unaffected: the chosen kernels are fixed in the plan.
+ * appends the winner to the cache.  Without a request, the cache is read only
+ * when $WSFFT_TUNE_CACHE is set, so by default a plan's kernels depend on its
+ * arguments alone.  WSFFT_TUNE=0 disables both, and the diagnostic
+ * WSFFT_TUNE_FORCE=<v> selects variant v wherever it exists.  Execution is
+ * unaffected: the chosen kernels are fixed in the plan.
  */
 
 /*
@@ -148,7 +158,8 @@ wsfft_status_t wsfft_execute_inverse(wsfft_plan_t plan, const void* in, void* ou
  * second passes, then all third (fewer launches when shapes allow), so the
  * whole batch is a handful of launches that a HIP graph can capture.  The
  * same plan may appear several times (e.g. one plan over many pencils);
- * plans with a work buffer may not.  When every entry uses the same plan and
+ * entries whose call would use their plan's work buffer (see above) may not
+ * (WSFFT_ERROR_INVALID_VALUE).  When every entry uses the same plan and
  * both in[i] and out[i] advance by exactly one array per entry, each pass is
  * a single launch over the whole batch.  Validation covers every entry
  * before any work is enqueued.
@@ -160,7 +171,9 @@ wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const
  * transform wsfft_execute (mode 0), wsfft_execute_adjoint (1) or
  * wsfft_execute_inverse (2) would run, with the same buffers.  Running every
  * index in order equals the full call; one index alone is for per-pass timing
- * and profiling. */
+ * and profiling.  On a real plan, mode 0 indexes the passes of
+ * wsfft_execute_r2c, modes 1 and 2 those of wsfft_execute_c2r and
+ * wsfft_execute_c2r_inverse (4-byte alignment is checked for both buffers). */
 wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const void* in, void* out,
                                   hipStream_t stream);
 
@@ -180,9 +193,15 @@ wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const 
  * are shared by its launches).  Supported: WSFFT_C64 plans whose axes are 32,
  * 64, 96, 128 or 256 long (or 1), one effective sign across the batch; other
  * batches return WSFFT_ERROR_UNSUPPORTED_SIZE and should use
- * wsfft_execute_batched.  Dependency waits are bounded: if one ever timed out,
- * the results are invalid and wsfft_batch_plan_check reports it (it
- * synchronises with the device).  NULL on error (wsfft_batch_get_last_error).
+ * wsfft_execute_batched.  Dependency waits are bounded: a launch in which one
+ * timed out has invalid results and is counted on the device;
+ * wsfft_batch_plan_check synchronises the device, reports whether any launch
+ * since the plan's creation or the previous check timed out, and clears the
+ * count.  Each launch starts with fresh counters, so a timed-out launch does
+ * not affect later ones.  wsfft_batch_plan_set_spin_limit (a diagnostic)
+ * sets the polls after which a wait gives up (default 2^22); a tiny limit
+ * forces timeouts from the host, and the launch still runs every tile and
+ * exits.  NULL on error (wsfft_batch_get_last_error).
  */
 typedef struct wsfft_batch_plan_s* wsfft_batch_plan_t;
 wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans, const void* const* in,
@@ -191,16 +210,57 @@ wsfft_status_t wsfft_batch_get_last_error(void);
 wsfft_status_t wsfft_batch_execute(wsfft_batch_plan_t batch, hipStream_t stream);
 int64_t wsfft_batch_plan_tiles(wsfft_batch_plan_t batch);      /* work items per execution; -1 invalid */
 wsfft_status_t wsfft_batch_plan_check(wsfft_batch_plan_t batch, int* timed_out);
+wsfft_status_t wsfft_batch_plan_set_spin_limit(wsfft_batch_plan_t batch, unsigned polls);
 void wsfft_batch_plan_destroy(wsfft_batch_plan_t batch);
+
+/*
+ * Real input and output (complex64 storage, FP32 arithmetic).  The paper's
+ * transform (Section 1) of a real array is Hermitian, X[-k] = conj(X[k]), so
+ * the bins kx = 0 .. nx/2 determine it: the half spectrum, an
+ * (nx/2 + 1) x ny x nz complex64 array, x fastest (the shape (nz, ny,
+ * nx/2 + 1) of a contiguous tensor).  The paper evaluates complex data only
+ * (Section 5); these calls halve the bytes every pass moves for real data.
+ *
+ * wsfft_plan_create_real: nx even, 4 <= nx <= 32768, every axis 2^a 3^b and
+ * at most WSFFT_MAX_AXIS (ny, nz longer than 1024 split into two passes
+ * through a plan-owned work buffer of one half spectrum); flags must be 0.
+ * NULL on error (wsfft_get_last_error).  The x pass transforms the nx reals
+ * of a pencil as nx/2 complex pairs and recombines the even and odd halves;
+ * the y and z passes are the complex passes over the half spectrum.
+ *
+ * wsfft_execute_r2c: out = the half spectrum of the forward (sign -1),
+ * unnormalised transform of the real array `in` (nx*ny*nz FP32, 4-byte
+ * aligned); out: (nx/2+1)*ny*nz complex64, 8-byte aligned.  `in` is not
+ * written.
+ * wsfft_execute_c2r: out = the sign +1, unnormalised transform of the
+ * Hermitian extension of the half spectrum `in`: sign +1 DFTs along z and y
+ * as given, then along x the extension Y[k], conj(Y[nx-k]) with the real
+ * parts of Y[0] and Y[nx/2] (their imaginary parts are ignored).  `in` is
+ * overwritten (its y and z passes run in place there); out: nx*ny*nz FP32.
+ * wsfft_execute_c2r_inverse: the same times 1/(nx*ny*nz), so that
+ * c2r_inverse(r2c(a)) = a.
+ * `in` and `out` must not overlap (in == out returns
+ * WSFFT_ERROR_INVALID_VALUE); wsfft_execute and the complex calls return
+ * WSFFT_ERROR_INVALID_VALUE for a real plan, and the real calls for a complex
+ * plan.  Enqueue only, like every execute call.
+ * wsfft_plan_is_real: 1 for a real plan, 0 for a complex one, -1 invalid.
+ */
+wsfft_plan_t wsfft_plan_create_real(int64_t nx, int64_t ny, int64_t nz, unsigned flags);
+wsfft_status_t wsfft_execute_r2c(wsfft_plan_t plan, const float* in, void* out, hipStream_t stream);
+wsfft_status_t wsfft_execute_c2r(wsfft_plan_t plan, void* in, float* out, hipStream_t stream);
+wsfft_status_t wsfft_execute_c2r_inverse(wsfft_plan_t plan, void* in, float* out, hipStream_t stream);
+int wsfft_plan_is_real(wsfft_plan_t plan);
 
 /* S of the stored 2^-S scaling (0 for WSFFT_C64); -1 for an invalid plan. */
 int wsfft_plan_scale_log2(wsfft_plan_t plan);
 
-/* Number of HBM passes one execute makes; -1 for an invalid plan. */
+/* Number of HBM passes one execute makes (real plans: wsfft_execute_r2c);
+ * -1 for an invalid plan. */
 int wsfft_plan_num_passes(wsfft_plan_t plan);
 
-/* Bytes of plan-owned device work buffer (0 unless an axis needs two passes
- * and cannot run in place); -1 for an invalid plan. */
+/* Bytes of plan-owned device work buffer (one array, for real plans one
+ * half spectrum, if an axis is split into two passes, else 0); -1 for an
+ * invalid plan. */
 int64_t wsfft_plan_work_bytes(wsfft_plan_t plan);
 
 /* Writes a one-line, NUL-terminated description of the pass schedule into

@@ -33,19 +33,32 @@ wsfft_status_t wsfft_complex_real_part(const void* in, float* out, int64_t n, hi
  * is real, so the operation is its own adjoint. */
 wsfft_status_t wsfft_poisson_symbol(void* data, int64_t nx, int64_t ny, int64_t nz, hipStream_t stream);
 
-/* The whole solve in six passes: u = Re(F^{-1}[-F[f](k) / |k|^2]) (k = 0
- * mode zero, wavenumbers as above, F^{-1} including 1/N).  The first forward
- * pass reads the real input, the last forward pass applies the multiplier
- * as it stores, and the last inverse pass stores only the real part, so no
- * separate elementwise pass runs.  plan: a WSFFT_C64 plan of the grid
- * (nx, ny, nz), any sign.  f, u: nx*ny*nz FP32 device arrays (x fastest,
- * 4-byte aligned; f and u may be the same array).  work: caller-owned device
- * buffer of nx*ny*nz complex64 (8-byte aligned), disjoint from f and u.
- * Enqueues six launches on `stream`; no allocation or synchronisation.
- * Returns WSFFT_ERROR_UNSUPPORTED_SIZE unless every axis is longer than 1
- * and has a fused kernel (32, 64, 128, 256, 512 or 1024 points); callers
- * then compose the solve from the plan and the three calls above.  The
- * operator is linear and self-adjoint, so its adjoint is the same call. */
+/* The whole solve u = Re(F^{-1}[-F[f](k) / |k|^2]) (k = 0 mode zero,
+ * wavenumbers as above, F^{-1} including 1/N) without separate elementwise
+ * passes.
+ *
+ * With a real plan of the grid (wsfft_plan_create_real(nx, ny, nz, 0)): five
+ * passes over the half spectrum, each moving about half the bytes of a
+ * complex pass: the R2C x pass reads f, the forward y pass, one z pass that
+ * transforms each z pencil forward, applies the multiplier (kx = 0 .. nx/2)
+ * and transforms it back, the inverse y pass, and the C2R x pass that stores
+ * u with 1/N.  work: (nx/2+1)*ny*nz complex64.  The fused z pass exists for
+ * nz of 32, 64, 128, 256, 512 or 1024 points.
+ *
+ * With a WSFFT_C64 complex plan of the grid (any sign): six complex passes;
+ * the first forward pass reads the real input, the last forward pass
+ * applies the multiplier as it stores, and the last inverse pass stores only
+ * the real part.  work: nx*ny*nz complex64.  Every axis needs a fused kernel
+ * (32, 64, 128, 256, 512 or 1024 points).
+ *
+ * f, u: nx*ny*nz FP32 device arrays (x fastest, 4-byte aligned; f and u may
+ * be the same array).  work: caller-owned, 8-byte aligned, disjoint from f
+ * and u.  Enqueues the launches on `stream`; no allocation or
+ * synchronisation.  Returns WSFFT_ERROR_UNSUPPORTED_SIZE for grids without
+ * the fused kernels (every axis must be longer than 1 and, for real plans,
+ * no axis split); callers then compose the solve from a plan and the three
+ * calls above.  The operator is linear and self-adjoint, so its adjoint is
+ * the same call. */
 wsfft_status_t wsfft_poisson_solve(wsfft_plan_t plan, const float* f, float* u, void* work, hipStream_t stream);
 
 #ifdef __cplusplus

@@ -80,11 +80,17 @@ _batch_error = _sig("wsfft_batch_get_last_error", _int, [])
 _batch_execute = _sig("wsfft_batch_execute", _int, [_vp, _vp])
 _batch_tiles = _sig("wsfft_batch_plan_tiles", _i64, [_vp])
 _batch_check = _sig("wsfft_batch_plan_check", _int, [_vp, ctypes.POINTER(_int)])
+_batch_spin = _sig("wsfft_batch_plan_set_spin_limit", _int, [_vp, ctypes.c_uint])
 _batch_destroy = _sig("wsfft_batch_plan_destroy", None, [_vp])
 _real_to_complex = _sig("wsfft_real_to_complex", _int, [_vp, _vp, _i64, _vp])
 _complex_real_part = _sig("wsfft_complex_real_part", _int, [_vp, _vp, _i64, _vp])
 _poisson_symbol = _sig("wsfft_poisson_symbol", _int, [_vp, _i64, _i64, _i64, _vp])
 _poisson_solve = _sig("wsfft_poisson_solve", _int, [_vp, _vp, _vp, _vp, _vp])
+_plan_create_real = _sig("wsfft_plan_create_real", _vp, [_i64, _i64, _i64, ctypes.c_uint])
+_execute_r2c = _sig("wsfft_execute_r2c", _int, [_vp, _vp, _vp, _vp])
+_execute_c2r = _sig("wsfft_execute_c2r", _int, [_vp, _vp, _vp, _vp])
+_execute_c2r_inverse = _sig("wsfft_execute_c2r_inverse", _int, [_vp, _vp, _vp, _vp])
+_plan_is_real = _sig("wsfft_plan_is_real", _int, [_vp])
 
 
 def _check(st: int, what: str) -> None:
@@ -277,14 +283,108 @@ class BatchPlan:
         _check(_batch_execute(self._h, _stream(stream)), "batch_execute")
 
     def timed_out(self) -> bool:
-        """True if a dependency wait ever timed out (synchronises)."""
+        """True if a dependency wait of any launch since creation or the
+        previous call timed out; clears that record (synchronises)."""
         flag = _int(0)
         _check(_batch_check(self._h, ctypes.byref(flag)), "batch_plan_check")
         return bool(flag.value)
 
+    def set_spin_limit(self, polls: int) -> None:
+        """Polls after which a dependency wait gives up (diagnostic)."""
+        _check(_batch_spin(self._h, int(polls)), "batch_plan_set_spin_limit")
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             _batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RealPlan:
+    """A real plan (``wsfft_plan_create_real``): the half spectrum of a real
+    nx x ny x nz array (complex64, shape (nz, ny, nx/2 + 1)) and back.
+
+    ``r2c(x)``: float32 (nz, ny, nx) -> complex64 half spectrum, forward sign,
+    unnormalised.  ``c2r(X)``: half spectrum -> float32, sign +1, unnormalised
+    (``inverse=True``: times 1/N, the inverse of ``r2c``); the C2R transform
+    overwrites its input."""
+
+    def __init__(self, nx: int, ny: int = 1, nz: int = 1, flags: int = 0):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.nxh = self.nx // 2 + 1
+        self.device = torch.cuda.current_device()
+        h = _plan_create_real(self.nx, self.ny, self.nz, int(flags))
+        if not h:
+            raise WsfftError(_get_last_error(), f"plan_create_real({nx},{ny},{nz})")
+        self._h = h
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    @property
+    def size(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def half_size(self) -> int:
+        return self.nxh * self.ny * self.nz
+
+    @property
+    def num_passes(self) -> int:
+        return _num_passes(self._h)
+
+    @property
+    def work_bytes(self) -> int:
+        return _work_bytes(self._h)
+
+    def half_shape(self, real_shape) -> tuple:
+        return tuple(real_shape[:-1]) + (self.nxh,)
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        _check(_describe(self._h, buf, len(buf)), "plan_describe")
+        return buf.value.decode()
+
+    @staticmethod
+    def _check(t, dtype, n, name):
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} device tensor")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} elements, plan wants {n}")
+
+    def r2c(self, x, out=None, stream=None):
+        self._check(x, torch.float32, self.size, "input")
+        if out is None:
+            out = torch.empty(self.half_shape(x.shape), dtype=torch.complex64, device=x.device)
+        self._check(out, torch.complex64, self.half_size, "output")
+        _check(_execute_r2c(self._h, x.data_ptr(), out.data_ptr(), _stream(stream)), "execute_r2c")
+        return out
+
+    def c2r(self, X, out=None, stream=None, inverse: bool = False):
+        """Overwrites X."""
+        self._check(X, torch.complex64, self.half_size, "input")
+        if out is None:
+            out = torch.empty(tuple(X.shape[:-1]) + (self.nx,), dtype=torch.float32, device=X.device)
+        self._check(out, torch.float32, self.size, "output")
+        fn = _execute_c2r_inverse if inverse else _execute_c2r
+        _check(fn(self._h, X.data_ptr(), out.data_ptr(), _stream(stream)), "execute_c2r")
+        return out
+
+    def execute_pass(self, index: int, x, out, mode: int = 0, stream=None):
+        """Only pass `index` of r2c (mode 0) or c2r (1; 2 with 1/N)."""
+        _check(_execute_pass(self._h, int(index), int(mode), x.data_ptr(), out.data_ptr(), _stream(stream)),
+               "execute_pass")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -300,16 +400,52 @@ _cache: dict = {}
 _cache_mu = threading.Lock()
 
 
-def get_plan(x: torch.Tensor, sign: int = -1, flags: int = 0) -> Plan:
-    dt = {torch.complex64: C64, torch.float16: C16_FP16, torch.bfloat16: C16_BF16}[x.dtype]
-    key = (shape_xyz(x.shape, dt), dt, sign, flags, x.device.index)
+def _cached_plan(xyz, dt: int, sign: int, flags: int, device: torch.device) -> Plan:
+    key = (tuple(xyz), dt, sign, flags, device.index)
     with _cache_mu:
         p = _cache.get(key)
         if p is None:
-            with torch.cuda.device(x.device):
+            with torch.cuda.device(device):
                 p = Plan(*key[0], dtype=dt, sign=sign, flags=flags)
             _cache[key] = p
         return p
+
+
+def _cached_real_plan(xyz, device: torch.device) -> RealPlan:
+    key = ("real", tuple(xyz), device.index)
+    with _cache_mu:
+        p = _cache.get(key)
+        if p is None:
+            with torch.cuda.device(device):
+                p = RealPlan(*xyz)
+            _cache[key] = p
+        return p
+
+
+def _real_xyz(shape):
+    s = tuple(shape)
+    if not 1 <= len(s) <= 3:
+        raise ValueError("rank 1..3 only")
+    s = (1,) * (3 - len(s)) + s
+    return s[2], s[1], s[0]
+
+
+def rfftn(x: torch.Tensor) -> torch.Tensor:
+    """Half spectrum (last axis nx//2 + 1) of the unnormalised forward DFT of
+    a real float32 tensor of rank 1..3 (x = the last axis)."""
+    return _cached_real_plan(_real_xyz(x.shape), x.device).r2c(x.contiguous())
+
+
+def irfftn(X: torch.Tensor, nx: int) -> torch.Tensor:
+    """The inverse of :func:`rfftn` (1/N included) for a real last axis of nx
+    points; X is not modified."""
+    xyz = (int(nx),) + _real_xyz(X.shape)[1:]
+    return _cached_real_plan(xyz, X.device).c2r(X.contiguous().clone(), inverse=True)
+
+
+def get_plan(x: torch.Tensor, sign: int = -1, flags: int = 0) -> Plan:
+    dt = {torch.complex64: C64, torch.float16: C16_FP16, torch.bfloat16: C16_BF16}[x.dtype]
+    return _cached_plan(shape_xyz(x.shape, dt), dt, sign, flags, x.device)
 
 
 def fftn(x: torch.Tensor, sign: int = -1) -> torch.Tensor:
@@ -405,13 +541,38 @@ class PoissonSymbol(torch.autograd.Function):
         return PoissonSymbol.forward(ctx, g)
 
 
-def _poisson_fused(f: torch.Tensor):
-    """wsfft_poisson_solve on a (nz, ny, nx) float32 tensor, or None where the
-    grid has no fused kernels."""
-    plan = get_plan(torch.empty(f.shape, dtype=torch.complex64, device=f.device), -1)
+_work_cache: dict = {}
+
+
+def _workspace(shape, device, stream: int) -> torch.Tensor:
+    """A complex64 work array for the solve on this grid, device and stream,
+    allocated on first use and reused by every later call (forward and
+    backward alike): calls on one stream run in order, so they never overlap
+    in it."""
+    key = (tuple(shape), device.index, stream)
+    with _cache_mu:
+        w = _work_cache.get(key)
+        if w is None:
+            w = torch.empty(shape, dtype=torch.complex64, device=device)
+            _work_cache[key] = w
+        return w
+
+
+def _poisson_fused(f: torch.Tensor, path: str):
+    """wsfft_poisson_solve on a (nz, ny, nx) float32 tensor with a real plan
+    (path "real": five half-spectrum passes) or a complex plan ("complex":
+    six complex passes); None where the grid has no fused kernels."""
+    xyz = shape_xyz(f.shape, C64)
+    if path == "real":
+        plan = _cached_real_plan(xyz, f.device)
+        wshape = (xyz[2], xyz[1], xyz[0] // 2 + 1)
+    else:
+        plan = _cached_plan(xyz, C64, -1, 0, f.device)
+        wshape = tuple(f.shape)
     u = torch.empty_like(f)
-    work = torch.empty(f.shape, dtype=torch.complex64, device=f.device)
-    st = _poisson_solve(plan.handle, f.data_ptr(), u.data_ptr(), work.data_ptr(), _stream(None))
+    st_h = _stream(None)
+    work = _workspace(wshape, f.device, st_h)
+    st = _poisson_solve(plan.handle, f.data_ptr(), u.data_ptr(), work.data_ptr(), st_h)
     if st == 2:   # WSFFT_ERROR_UNSUPPORTED_SIZE
         return None
     _check(st, "poisson_solve")
@@ -423,22 +584,39 @@ class PoissonSolve(torch.autograd.Function):
     backward pass is the same solve applied to the incoming gradient."""
 
     @staticmethod
-    def forward(ctx, f):
-        return _poisson_fused(f.contiguous())
+    def forward(ctx, f, path: str = "real"):
+        ctx.path = path
+        return _poisson_fused(f.contiguous(), path)
 
     @staticmethod
     def backward(ctx, g):
-        return _poisson_fused(g.contiguous())
+        return _poisson_fused(g.contiguous(), ctx.path), None
 
 
-def poisson_solve(f: torch.Tensor, fused: bool = True) -> torch.Tensor:
+def poisson_solve(f: torch.Tensor, fused: bool = True, path: str = "auto") -> torch.Tensor:
     """u = Re(IFFT(-FFT(f)/|k|^2)) on the periodic box [0, 2*pi)^3, differentiable.
-    Grids with fused kernels run wsfft_poisson_solve (six passes); others, or
-    fused=False, compose the plan's transforms and the elementwise kernels."""
+
+    path "real": wsfft_poisson_solve with a real plan (five half-spectrum
+    passes); "complex": with a complex plan (six complex passes); "composed":
+    the complex plan's transforms and the elementwise kernels; "auto" (the
+    default): the first of these the grid supports.  fused=False is
+    "composed"."""
     if f.dtype != torch.float32 or not f.is_cuda or f.dim() != 3:
         raise TypeError("poisson_solve takes a (nz, ny, nx) float32 device tensor")
-    if fused and _poisson_fused_supported(tuple(f.shape)):
-        return PoissonSolve.apply(f)
+    if not fused:
+        path = "composed"
+    shape = tuple(f.shape)
+    if path == "auto":
+        path = ("real" if _poisson_real_supported(shape)
+                else "complex" if _poisson_fused_supported(shape) else "composed")
+    if path == "real" and not _poisson_real_supported(shape):
+        raise ValueError(f"grid {shape} has no fused half-spectrum solve")
+    if path == "complex" and not _poisson_fused_supported(shape):
+        raise ValueError(f"grid {shape} has no fused complex solve")
+    if path in ("real", "complex"):
+        return PoissonSolve.apply(f, path)
+    if path != "composed":
+        raise ValueError(f"unknown path {path!r}")
     z = RealToComplex.apply(f)
     F = FFTn.apply(z, -1)
     U = PoissonSymbol.apply(F)
@@ -451,3 +629,22 @@ _FUSED_LENGTHS = (32, 64, 128, 256, 512, 1024)
 
 def _poisson_fused_supported(shape) -> bool:
     return len(shape) == 3 and all(n in _FUSED_LENGTHS for n in shape)
+
+
+def _poisson_real_supported(shape) -> bool:
+    """(nz, ny, nx): the fused z pass of the half-spectrum solve exists for nz
+    in _FUSED_LENGTHS; nx is even (4 .. 32768) and ny at most 1024 (one pass)."""
+    if len(shape) != 3:
+        return False
+    nz, ny, nx = shape
+    return nz in _FUSED_LENGTHS and 1 < ny <= 1024 and _smooth23(ny) and nx % 2 == 0 and 4 <= nx <= 32768 \
+        and _smooth23(nx)
+
+
+def _smooth23(n: int) -> bool:
+    if n < 1:
+        return False
+    for p in (2, 3):
+        while n % p == 0:
+            n //= p
+    return n == 1

@@ -585,6 +585,16 @@ enum : int {
     kFlagPoisson = 64,      // strided layout, z pass of an (nx, ny, N) grid: every stored
                             // element is multiplied by -1/|k|^2 of its frequency (0 at k = 0)
     kFlagRealOut = 128,     // strided layout: only the real part is stored, as FP32
+    // Real input and output (complex64 storage; the half spectrum of a real
+    // array of 2N points along x is the N + 1 bins kx = 0 .. N):
+    kFlagR2C = 256,         // contiguous layout: pencil q holds 2N reals read as N complex
+                            // z[m] = a[2m] + i a[2m+1]; after the N-point FFT an epilogue
+                            // through LDS stores the N + 1 half-spectrum bins at q*os1_out
+    kFlagC2R = 512,         // contiguous layout: a prologue through LDS turns the N + 1 bins at
+                            // q*os1_in into the N-point spectrum whose inverse FFT is the 2N
+                            // reals as N complex pairs, stored at q*os1_out
+    kFlagSolveZ = 1024,     // strided layout, z pass of a Poisson solve: forward FFT, times
+                            // -1/|k|^2, inverse FFT (opposite sign) of each pencil in one tile
 };
 
 // -------------------------------------------------------------- pass args ---
@@ -608,8 +618,15 @@ struct PassArgs {
                           // 2: times W_M^(o1*e), table entry o1*e
     int32_t tstore;       // strided layout only: store columns as contiguous runs via LDS
     float scale;          // multiplies every stored value
-    int32_t sym_nx;       // kFlagPoisson: column c of the z pass is (x, y) = (c mod sym_nx, c div sym_nx)
-    int32_t sym_ny;
+    int32_t sym_nx;       // kFlagPoisson / kFlagSolveZ: column c of the z pass is
+    int32_t sym_ny;       //   (x, y) = (c mod sym_nx, c div sym_nx)
+    int32_t sym_half;     //   nonzero: the columns are a half spectrum, kx = x (else the wavenumber of x)
+    int32_t pad_;
+    // strided layout: nonzero flattens the columns over (column, o1) pairs:
+    // C counts flat_c * (the original O1) columns, column i is original column
+    // i mod flat_c of outer index i div flat_c (O1 = 1), so tiles run on across
+    // the outer index instead of leaving a ragged tile at each one (cs_out = 1)
+    int64_t flat_c;
 };
 
 // One array of a merged batch launch: the fields of a direct pass that differ
@@ -628,6 +645,30 @@ struct BatchTable {
     int32_t count;      // 0: a single-array launch described by PassArgs alone
     int32_t pad;
     ArrayDesc d[kMaxBatchDescs];
+};
+
+// Per-thread context of one tile.  Besides the element indices, the split
+// form of the addresses: element e of this thread's pencil or column is at
+// ib + (e - le_in) * ies + il (bytes), where ib and ies are the same for the
+// whole wave and il is a 32-bit per-lane offset; le_in is the part of e that
+// varies across the wave's lanes (j, or j * NB for paired slots).  Likewise
+// ob, oes, ol for the stored elements.  Lanes of a ragged tile past the last
+// pencil or column load the tile's first one instead (it always exists;
+// pencils are independent and such lanes never store), so split loads need
+// no per-element predicate.  split is false when a lane offset could exceed
+// 32 bits (strides of several GiB); the 64-bit element-index form is used
+// then.
+struct PassCtx {
+    int p, j;
+    bool valid;
+    bool split;
+    int64_t col;          // global column (strided) or pencil (contiguous)
+    int64_t o1;
+    int64_t base_in, base_out;
+    const char* ib;
+    char* ob;
+    int64_t ies, oes;
+    uint32_t il, ol;
 };
 
 // ------------------------------------------------------------ the kernel ---
@@ -650,8 +691,15 @@ struct PencilPass {
     static constexpr bool REALIN = (FLAGS & kFlagRealIn) != 0;
     static constexpr bool REALOUT = (FLAGS & kFlagRealOut) != 0;
     static constexpr bool POISSON = (FLAGS & kFlagPoisson) != 0;
+    static constexpr bool R2C = (FLAGS & kFlagR2C) != 0;
+    static constexpr bool C2R = (FLAGS & kFlagC2R) != 0;
+    static constexpr bool SOLVEZ = (FLAGS & kFlagSolveZ) != 0;
     static_assert(!REALIN || !STRIDED, "real input is read by contiguous passes");
     static_assert(!(REALOUT || POISSON) || (STRIDED && !FOURSTEP), "fused outputs are strided direct passes");
+    static_assert(!(R2C || C2R) || (!STRIDED && !FOURSTEP && !REALIN && sizeof(V) == 8),
+                  "real-data passes: contiguous pencils with FP32 values");
+    static_assert(!SOLVEZ || (STRIDED && !FOURSTEP && !POISSON && !REALOUT && sizeof(V) == 8),
+                  "the fused solve is a strided complex64 direct pass");
     static constexpr int64_t BI = REALIN ? 4 : IO::bytes;    // bytes per input element
     static constexpr int64_t BO = REALOUT ? 4 : IO::bytes;   // bytes per output element
     __device__ __forceinline__ static V gload(const void* p, int64_t i) {
@@ -725,17 +773,18 @@ struct PencilPass {
         return STRIDED ? e * LDS_ROW + p : p * LDS_ROW + e + (e >> PADSH);
     }
 
-    // Exchange round of the value in slot (t, r) when written after stage S
-    // (W) or read before stage S+1 (R): the round if it is the same for every
-    // thread j, else -1 (decided at run time).  Tables are built at compile
-    // time, so after unrolling each access is either kept in exactly one
-    // round or decided by one compare.
-    template <int S> struct Rounds {
-        int w[St<S>::NB][St<S>::R];
-        int r[St<S + 1>::NB][St<S + 1>::R];
+    // Exchange round of the value in slot (t, r) when written after stage SO
+    // (W) or read before stage SI (R; SI = SO + 1, or 0 when a second
+    // transform of the same pencils follows): the round if it is the same
+    // for every thread j, else -1 (decided at run time).  Tables are built at
+    // compile time, so after unrolling each access is either kept in exactly
+    // one round or decided by one compare.
+    template <int SO, int SI = SO + 1> struct Rounds {
+        int w[St<SO>::NB][St<SO>::R];
+        int r[St<SI>::NB][St<SI>::R];
         constexpr Rounds() : w(), r() {
-            using Q = St<S>;
-            using Q2 = St<S + 1>;
+            using Q = St<SO>;
+            using Q2 = St<SI>;
             for (int t = 0; t < Q::NB; ++t)
                 for (int rr = 0; rr < Q::R; ++rr) {
                     int h = -2;
@@ -762,29 +811,7 @@ struct PencilPass {
         }
     };
 
-    // Per-thread context of one tile.  Besides the element indices, the
-    // split form of the addresses: element e of this thread's pencil or
-    // column is at ib + (e - le_in) * ies + il (bytes), where ib and ies are
-    // the same for the whole wave and il is a 32-bit per-lane offset; le_in
-    // is the part of e that varies across the wave's lanes (j, or j * NB for
-    // paired slots).  Likewise ob, oes, ol for the stored elements.  Lanes of
-    // a ragged tile past the last pencil or column load the tile's first one
-    // instead (it always exists; pencils are independent and such lanes
-    // never store), so split loads need no per-element predicate.  split is
-    // false when a lane offset could exceed 32 bits (strides of several GiB);
-    // the 64-bit element-index form is used then.
-    struct Ctx {
-        int p, j;
-        bool valid;
-        bool split;
-        int64_t col;          // global column (strided) or pencil (contiguous)
-        int64_t o1;
-        int64_t base_in, base_out;
-        const char* ib;
-        char* ob;
-        int64_t ies, oes;
-        uint32_t il, ol;
-    };
+    using Ctx = PassCtx;
 
     // Twiddle table entry (global memory, 32-bit offset).
     __device__ __forceinline__ static V tw_at(const float2* tw, int i) {
@@ -818,14 +845,15 @@ struct PencilPass {
         }
     }
 
-    // Stage S outputs (vo) -> stage S+1 inputs (vi) through LDS, in K rounds
-    // of ROWS rows.  lead: the LDS may still be read by the previous exchange.
-    template <int S>
+    // Stage S outputs (vo) -> stage SI inputs (vi, by default stage S+1)
+    // through LDS, in K rounds of ROWS rows.  lead: the LDS may still be read
+    // by the previous exchange.
+    template <int S, int SI = S + 1>
     __device__ __forceinline__ static void exchange(V* lds, const V* vo, V* vi, int p, int j,
                                                     bool lead) {
         using Q = St<S>;
-        using Q2 = St<S + 1>;
-        constexpr Rounds<S> RT{};
+        using Q2 = St<SI>;
+        constexpr Rounds<S, SI> RT{};
 #pragma unroll
         for (int h = 0; h < K; ++h) {
             if (lead || h > 0) __syncthreads();
@@ -876,10 +904,11 @@ struct PencilPass {
     __device__ __forceinline__ static float wavenumber(int64_t i, int64_t n) {
         return (float)(i < (n + 1) / 2 ? i : i - n);
     }
-    // kx^2 + ky^2 of this thread's column of the z pass (kFlagPoisson).
+    // kx^2 + ky^2 of this thread's column of the z pass (kFlagPoisson,
+    // kFlagSolveZ); the columns of a half spectrum are kx = 0 .. nx/2.
     __device__ __forceinline__ static float kxy2_of(const Ctx& c, const PassArgs& a) {
         const int64_t x = c.col % a.sym_nx, y = c.col / a.sym_nx;
-        const float kx = wavenumber(x, a.sym_nx), ky = wavenumber(y, a.sym_ny);
+        const float kx = a.sym_half ? (float)x : wavenumber(x, a.sym_nx), ky = wavenumber(y, a.sym_ny);
         return kx * kx + ky * ky;
     }
     // A stored value: the pass scale and, for the Poisson z pass, -1/|k|^2 of
@@ -895,10 +924,135 @@ struct PencilPass {
         return v;
     }
 
+    // kFlagR2C epilogue.  The N-point transform Z of z[m] = a[2m] + i a[2m+1]
+    // carries the transforms of the even and odd samples,
+    // E = (Z[k] + conj Z[N-k]) / 2 and O = (Z[k] - conj Z[N-k]) / (2i), and
+    // the 2N-point transform of a is X[k] = E + W^k O, X[N-k] = conj(E - W^k O)
+    // with W = exp(SIGN 2 pi i / 2N); each thread takes pairs (k, N-k),
+    // k = 0 .. N/2 (k = 0 gives bins 0 and N).  a.tw4 entry k (k <= N/2)
+    // holds exp(-2 pi i k / 2N).
+    template <int S>
+    __device__ __forceinline__ static void store_r2c(V* lds, const V* v, const Ctx& c, const PassArgs& a) {
+        using Q = St<S>;
+        __syncthreads();   // the last exchange's reads are done
+#pragma unroll
+        for (int t = 0; t < Q::NB; ++t) {
+            const int b = Q::bf(c.j, t);
+            if (!Q::FULL && b >= Q::NBF) continue;
+#pragma unroll
+            for (int r = 0; r < Q::R; ++r) lds[lidx(c.p, b + r * Q::NBF)] = v[t * Q::R + r];
+        }
+        __syncthreads();
+        if (!c.valid) return;
+        constexpr int H = N / 2;
+        constexpr int PER = (H + 1 + T - 1) / T;
+        const char* twb = reinterpret_cast<const char*>(a.tw4);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int k = c.j + i * T;
+            if (k > H) continue;
+            const float2 zk = lds[lidx(c.p, k)];
+            const float2 zm = lds[lidx(c.p, k == 0 ? 0 : N - k)];
+            const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));   // (Z[k] - conj Z[N-k]) / 2
+            const float2 o = make_float2(d.y, -d.x);                                      // -i times that
+            const f32x2 wv = *gload_at<f32x2>(twb, (uint32_t)k * 8u);
+            float2 w = make_float2(wv.x, wv.y);
+            if (SIGN > 0) w.y = -w.y;
+            const float2 wo = cmul(o, w);
+            gstore(a.dst, c.base_out + k, oscale(cadd(e, wo), a));
+            if (k != N - k) {
+                const float2 m = csub(e, wo);
+                gstore(a.dst, c.base_out + (N - k), oscale(make_float2(m.x, -m.y), a));
+            }
+        }
+    }
+
+    // kFlagC2R prologue: the inverse of the epilogue above.  From the N + 1
+    // half-spectrum bins X of a pencil, with A = X[k] and B = conj X[N-k],
+    // Z[k] = (A + B) + i V^k (A - B) and Z[N-k] = conj((A + B) - i V^k (A - B)),
+    // V = exp(SIGN 2 pi i / 2N), is the N-point spectrum whose transform (sign
+    // SIGN, unnormalised) is z[m] = a[2m] + i a[2m+1], a the 2N-point transform
+    // of the Hermitian extension of X.  Bins 0 and N contribute their real
+    // parts only (a Hermitian spectrum has no imaginary part there).  Z goes
+    // to LDS in natural order and the first stage reads it from there.
+    __device__ __forceinline__ static void load_c2r(V* v, const Ctx& c, const PassArgs& a, V* lds) {
+        constexpr int H = N / 2;
+        constexpr int PER = (H + 1 + T - 1) / T;
+        const char* twb = reinterpret_cast<const char*>(a.tw4);
+        // lanes past the last pencil read the tile's first pencil (never stored)
+        const int64_t base = c.valid ? c.base_in : (c.col - c.p) * a.os1_in;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int k = c.j + i * T;
+            if (k > H) continue;
+            float2 A = gload(a.src, base + k);
+            float2 Bc = gload(a.src, base + (N - k));
+            if (k == 0) {
+                A.y = 0.f;
+                Bc.y = 0.f;
+            }
+            const float2 B = make_float2(Bc.x, -Bc.y);
+            const f32x2 wv = *gload_at<f32x2>(twb, (uint32_t)k * 8u);
+            float2 w = make_float2(wv.x, wv.y);
+            if (SIGN > 0) w.y = -w.y;
+            const float2 t1 = cadd(A, B);
+            const float2 t2 = crot90<1>(cmul(csub(A, B), w));   // i V^k (A - B)
+            lds[lidx(c.p, k)] = cadd(t1, t2);
+            if (k != 0 && k != N - k) {
+                const float2 m = csub(t1, t2);
+                lds[lidx(c.p, N - k)] = make_float2(m.x, -m.y);
+            }
+        }
+        __syncthreads();
+        using Q = St<0>;
+#pragma unroll
+        for (int t = 0; t < Q::NB; ++t) {
+            const int b = Q::bf(c.j, t);
+            if (!Q::FULL && b >= Q::NBF) continue;
+#pragma unroll
+            for (int r = 0; r < Q::R; ++r) v[t * Q::R + r] = lds[lidx(c.p, b + r * Q::NBF)];
+        }
+    }
+
+    // kFlagSolveZ: after the forward stages, multiply every value by
+    // -1/|k|^2 of its frequency (0 at k = 0), then run the stages of the
+    // opposite sign on the same registers (through LDS when the last and
+    // the first stage hold different elements), which end in the store.
+    template <int S>
+    __device__ __forceinline__ static void solve_z(V* lds, V* v, const Ctx& c, const PassArgs& a) {
+        using Q = St<S>;
+        const float kxy2 = kxy2_of(c, a);
+#pragma unroll
+        for (int t = 0; t < Q::NB; ++t) {
+            const int b = Q::bf(c.j, t);
+            if (!Q::FULL && b >= Q::NBF) continue;
+#pragma unroll
+            for (int r = 0; r < Q::R; ++r) {
+                const float kz = wavenumber(b + r * Q::NBF, N);
+                const float k2 = kxy2 + kz * kz;
+                const float m = k2 > 0.f ? -1.0f / k2 : 0.f;
+                v[t * Q::R + r] = cscale(v[t * Q::R + r], m);
+            }
+        }
+        using Inv = PencilPass<N, T, P, STRIDED, IO, -SIGN, (FLAGS & ~kFlagSolveZ), K, PLAN>;
+        if constexpr (RD.r[0] == RD.r[NS - 1]) {
+            Inv::template stages<0>(lds, v, c, a, a.tw, true);
+        } else {
+            V w[maxv()];
+            exchange<S, 0>(lds, v, w, c.p, c.j, true);
+            Inv::template stages<0>(lds, w, c, a, a.tw, true);
+        }
+    }
+
     template <int S>
     __device__ __forceinline__ static void store_last(V* lds, const V* v, const Ctx& c,
                                                       const PassArgs& a) {
         using Q = St<S>;
+        if constexpr (R2C) {
+            store_r2c<S>(lds, v, c, a);
+            return;
+        }
         if (FOURSTEP && STRIDED && a.tstore) {
             // Results go to LDS in natural element order, ROWS rows per round,
             // and each column leaves as contiguous runs of ROWS elements.
@@ -1038,15 +1192,19 @@ struct PencilPass {
         }
     }
 
-    // Stages S .. NS-1; v holds the inputs of stage S.
+    // Stages S .. NS-1; v holds the inputs of stage S.  lead0: the LDS may
+    // still be read by earlier work of the tile before the first exchange
+    // (later exchanges always synchronise first).
     template <int S>
     __device__ __forceinline__ static void stages(V* lds, V* v, const Ctx& c, const PassArgs& a,
-                                                  const float2* tw) {
+                                                  const float2* tw, bool lead0 = C2R) {
         butterflies<S>(v, c.j, tw);
         if constexpr (S + 1 < NS) {
             V w[maxv()];
-            exchange<S>(lds, v, w, c.p, c.j, S > 0);
-            stages<S + 1>(lds, w, c, a, tw);
+            exchange<S>(lds, v, w, c.p, c.j, S > 0 || lead0);
+            stages<S + 1>(lds, w, c, a, tw, false);
+        } else if constexpr (SOLVEZ) {
+            solve_z<S>(lds, v, c, a);
         } else {
             store_last<S>(lds, v, c, a);
         }
@@ -1067,18 +1225,33 @@ struct PencilPass {
             c.o1 = rest % a.O1;
             const int64_t o2 = rest / a.O1;
             c.valid = c.col < a.C;
-            c.base_in = c.col + c.o1 * a.os1_in + o2 * a.os2_in;
-            c.base_out = c.col * a.cs_out + c.o1 * a.os1_out + o2 * a.os2_out;
+            // element offsets (before the o1, o2 terms) of the tile's first
+            // column and of this lane's column; flattened columns step to the
+            // next outer index every flat_c columns (cs_out = 1)
+            int64_t in0 = col0, inp = c.col, out0 = col0 * a.cs_out, outp = c.col * a.cs_out;
+            int64_t span = P;   // bound of the lane offsets within a row
+            if (a.flat_c != 0) {
+                const int64_t q0 = col0 / a.flat_c, qp = c.col / a.flat_c;
+                in0 = col0 + q0 * (a.os1_in - a.flat_c);
+                inp = c.col + qp * (a.os1_in - a.flat_c);
+                out0 = col0 + q0 * (a.os1_out - a.flat_c);
+                outp = c.col + qp * (a.os1_out - a.flat_c);
+                // a tile spans at most P / flat_c + 2 outer indices
+                span = P + (P / a.flat_c + 1) * (a.os1_in > a.os1_out ? a.os1_in : a.os1_out);
+            }
+            c.base_in = inp + c.o1 * a.os1_in + o2 * a.os2_in;
+            c.base_out = outp + c.o1 * a.os1_out + o2 * a.os2_out;
             // the wave's lanes hold rows jw .. jw + JS - 1 (j grows with tid)
             constexpr int JS = (64 + P - 1) / P + 1;
             const int jw = (wave * 64) / P, jl = c.j - jw;
             c.ies = a.es_in * BI;
             c.oes = a.es_out * BO;
-            c.ib = static_cast<const char*>(a.src) + (col0 + c.o1 * a.os1_in + o2 * a.os2_in + jw * a.es_in) * BI;
-            c.ob = static_cast<char*>(a.dst) + (col0 * a.cs_out + c.o1 * a.os1_out + o2 * a.os2_out + jw * a.es_out) * BO;
-            c.il = (uint32_t)(((c.valid ? c.p : 0) + jl * a.es_in) * BI);
-            c.ol = (uint32_t)((c.p * a.cs_out + jl * a.es_out) * BO);
-            c.split = (P * BI + JS * c.ies) < (int64_t(1) << 32) && (P * a.cs_out * BO + JS * c.oes) < (int64_t(1) << 32);
+            c.ib = static_cast<const char*>(a.src) + (in0 + c.o1 * a.os1_in + o2 * a.os2_in + jw * a.es_in) * BI;
+            c.ob = static_cast<char*>(a.dst) + (out0 + c.o1 * a.os1_out + o2 * a.os2_out + jw * a.es_out) * BO;
+            c.il = (uint32_t)(((c.valid ? inp - in0 : 0) + jl * a.es_in) * BI);
+            c.ol = (uint32_t)(((outp - out0) + jl * a.es_out) * BO);
+            c.split = (span * BI + JS * c.ies) < (int64_t(1) << 32) &&
+                      (span * a.cs_out * BO + JS * c.oes) < (int64_t(1) << 32);
         } else {
             c.j = tid % T;
             c.p = tid / T;
@@ -1181,7 +1354,8 @@ struct PencilPass {
     __device__ __forceinline__ static void run_tile(const PassArgs& a, int64_t t, V* lds) {
         const Ctx c = make_ctx(a, t);
         V v[maxv()];
-        load_first(v, c, a);
+        if constexpr (C2R) load_c2r(v, c, a, lds);
+        else load_first(v, c, a);
         scale_loaded(v, a);
         stages<0>(lds, v, c, a, a.tw);
     }

@@ -20,11 +20,15 @@ struct PassKernel {
     // batch of direct passes (PassArgs supplies the shared fields)
     hipError_t (*launch)(const PassArgs&, const BatchTable* bt, dim3 grid, hipStream_t);
     hipError_t (*prepare)();   // one-time function attributes
-    int fused;          // 0: plain pass; Poisson solve passes (complex64 only):
-                        // 1 real input, 2 times -1/|k|^2, 3 real output
+    int fused;          // 0: plain pass; complex64 only: Poisson solve passes
+                        // 1 real input, 2 times -1/|k|^2, 3 real output;
+                        // 4 R2C x pass, 5 C2R x pass, 6 fused solve z pass
 };
 
-enum FusedKind { kFusedNone = 0, kFusedRealIn = 1, kFusedPoisson = 2, kFusedRealOut = 3 };
+enum FusedKind {
+    kFusedNone = 0, kFusedRealIn = 1, kFusedPoisson = 2, kFusedRealOut = 3,
+    kFusedR2C = 4, kFusedC2R = 5, kFusedSolveZ = 6
+};
 
 // NULL when no kernel of that length/layout/variant exists.
 const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strided, bool four_step,
@@ -45,5 +49,10 @@ WSFFT_DECLARE_FIND(find_pass_f16m_pos)
 // sign -1, real output with sign +1).  NULL when none exists for n.
 const PassKernel* find_fused_c64_neg(int n, bool strided, int fused);
 const PassKernel* find_fused_c64_pos(int n, bool strided, int fused);
+// Real-data kernels (complex64): R2C x passes and fused solve z passes with
+// sign -1 (_neg), C2R x passes with sign +1 (_pos); n is the pencil length of
+// the complex transform (half the real length for the x passes).
+const PassKernel* find_real_c64_neg(int n, bool strided, int fused);
+const PassKernel* find_real_c64_pos(int n, bool strided, int fused);
 
 }  // namespace wsfft

@@ -15,7 +15,9 @@
 // publish it when it claims its next ticket or leaves.  The wait is bounded;
 // on timeout the launch records an error and finishes.  The last workgroup to
 // leave resets the counters, so the next launch on the same counters starts
-// from zero.
+// from zero: it moves a recorded error into a count of failed launches, which
+// only the host reads and clears, so one timed-out launch never makes a
+// later launch skip its waits.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -176,6 +178,10 @@ __global__ __launch_bounds__(kPT, 3) void persist_kernel(const PersistPass* __re
         if (prevf + 1 == gridDim.x) {
             for (int i = 0; i < kPersistMaxLevels; ++i) ctr->done[i] = 0;
             ctr->ticket = 0;
+            if (__hip_atomic_load(&ctr->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                __hip_atomic_fetch_add(&ctr->failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ctr->error, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(&ctr->finished, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }

@@ -29,8 +29,8 @@ struct PersistLevels {
 struct PersistCounters {
     unsigned ticket;     // next work item
     unsigned finished;   // workgroups that left
-    unsigned error;      // nonzero: a dependency wait timed out
-    unsigned pad;
+    unsigned error;      // nonzero: a dependency wait of the running launch timed out
+    unsigned failed;     // launches that ended with `error` set (kept until the host clears it)
     unsigned done[kPersistMaxLevels];   // tiles published per level
 };
 

@@ -147,7 +147,10 @@ struct wsfft_plan_s {
     unsigned flags;
     int device;
     int scale_log2;
-    std::vector<Pass> passes;
+    std::vector<Pass> passes;     // c2c plans: the transform; real plans: the R2C passes
+    bool real = false;            // created by wsfft_plan_create_real
+    std::vector<Pass> cpasses;    // real plans: the C2R passes (the x pass last)
+    int nsplit = 0;               // axes split into two passes (four-step)
     float2* tw_dev = nullptr;     // all twiddle tables, one block
     void* work = nullptr;         // four-step work buffer (or null)
     int64_t work_bytes = 0;
@@ -247,25 +250,108 @@ const char* kind_name(wsfft_dtype_t d, unsigned flags) {
     return d == WSFFT_C64 ? "c64" : (d == WSFFT_C16_FP16 ? "c16-fp16" : "c16-bf16");
 }
 
+void describe_passes(std::string& out, const std::vector<Pass>& passes) {
+    char buf[256];
+    for (const Pass& P : passes) {
+        const char* what = P.kern_neg->fused == kFusedR2C ? "r2c" : (P.kern_neg->fused == kFusedC2R ? "c2r" : "");
+        std::snprintf(buf, sizeof buf, " %c%s[%s%s n=%lld v%d wg=%d per=%d lds=%d grid=%u%s]", "xyz"[P.axis],
+                      P.four_step == 1 ? "A" : (P.four_step == 2 ? "B" : ""), what, P.strided ? "strided" : "contig",
+                      (long long)P.n, P.variant, P.kern_neg->threads, P.kern_neg->per_block, P.kern_neg->lds_bytes,
+                      P.grid.x, P.args.flat_c ? " flat" : "");
+        out += buf;
+    }
+}
+
 void describe_plan(wsfft_plan_s* plan) {
     char buf[256];
     std::snprintf(buf, sizeof buf, "%lldx%lldx%lld %s sign=%d S=%d:", (long long)plan->n[0], (long long)plan->n[1],
-                  (long long)plan->n[2], kind_name(plan->dtype, plan->flags), plan->sign, plan->scale_log2);
+                  (long long)plan->n[2], plan->real ? "real-c64" : kind_name(plan->dtype, plan->flags), plan->sign,
+                  plan->scale_log2);
     plan->desc = buf;
-    for (const Pass& P : plan->passes) {
-        std::snprintf(buf, sizeof buf, " %c%s[%s n=%lld v%d wg=%d per=%d lds=%d grid=%u]", "xyz"[P.axis],
-                      P.four_step == 1 ? "A" : (P.four_step == 2 ? "B" : ""), P.strided ? "strided" : "contig",
-                      (long long)P.n, P.variant, P.kern_neg->threads, P.kern_neg->per_block, P.kern_neg->lds_bytes,
-                      P.grid.x);
-        plan->desc += buf;
+    describe_passes(plan->desc, plan->passes);
+    if (plan->real) {
+        plan->desc += " | c2r:";
+        describe_passes(plan->desc, plan->cpasses);
     }
+}
+
+// WSFFT_LOG=1: print every created plan's schedule (passes, kernels, tiles)
+// to stderr.
+void log_plan(const std::string& desc) {
+    const char* e = std::getenv("WSFFT_LOG");
+    if (e && std::strcmp(e, "1") == 0) std::fprintf(stderr, "wsfft: plan %s\n", desc.c_str());
+}
+
+// Twiddle tables of a plan, one per distinct (kind, length, n1), laid out
+// back to back in one device block:
+//  kStage: the stage tables of the radix plans 0, 1, 2 of a pass length,
+//          len entries each (stage_tw_offset); a pass uses the block of its
+//          kernel's plan;
+//  kPlain: entry m is W_len^m (inter-pass twiddles of strided split axes);
+//  kMatrix: entry m is W_len^{(m div n1) * (m mod n1)}, the inter-pass
+//          twiddle of output position k1 + n1*y2 of pass A of a unit-stride
+//          split axis, so lanes that store consecutive outputs read
+//          consecutive entries;
+//  kHalf: entry m is W_len^m for m = 0 .. len/4, the recombination twiddles
+//          of the half-spectrum passes of a real axis of len points.
+enum { kStage = 0, kPlain = 1, kMatrix = 2, kHalf = 3 };
+struct TableSet {
+    struct Table { int kind; int64_t len, n1, off; };
+    std::vector<Table> tables;
+    int64_t total = 0;
+    int64_t get(int kind, int64_t len, int64_t n1 = 0) {
+        for (auto& t : tables)
+            if (t.kind == kind && t.len == len && t.n1 == n1) return t.off;
+        tables.push_back({kind, len, n1, total});
+        total += kind == kStage ? kTwPlans * len : (kind == kHalf ? len / 4 + 1 : len);
+        return tables.back().off;
+    }
+};
+
+// Evaluates every table of `ts` in FP64, rounds each entry once (nearest even)
+// to a format of `mant` stored significand bits and smallest normal exponent
+// `emin`, and copies the block to a new device allocation.
+wsfft_status_t upload_tables(const TableSet& ts, int mant, int emin, float2** dev) {
+    std::vector<float2> host((size_t)std::max<int64_t>(ts.total, 1));
+    auto put = [&](int64_t at, int64_t m, int64_t len) {
+        double re, im;
+        root_fp64(m, len, &re, &im);
+        host[(size_t)at] = make_float2((float)round_to_format(re, mant, emin), (float)round_to_format(im, mant, emin));
+    };
+    for (auto& t : ts.tables) {
+        if (t.kind == kStage) {
+            // entry (r-1)*Ns + k of stage s: W_{Ns*R}^{k*r} = W_len^{k*r*len/(Ns*R)}
+            for (int pl = 0; pl < kTwPlans; ++pl) {
+                const Radices rd = make_radices((int)t.len, pl);
+                const int64_t base = t.off + (int64_t)pl * t.len;
+                for (int st = 1; st < rd.n; ++st) {
+                    const int64_t R = rd.r[st], Ns = stage_ns(rd, st), tws = t.len / (Ns * R);
+                    const int64_t off = stage_tw_offset(rd, st);
+                    for (int64_t r = 1; r < R; ++r)
+                        for (int64_t k = 0; k < Ns; ++k) put(base + off + (r - 1) * Ns + k, k * r * tws, t.len);
+                }
+            }
+        } else if (t.kind == kHalf) {
+            for (int64_t m = 0; m <= t.len / 4; ++m) put(t.off + m, m, t.len);
+        } else {
+            for (int64_t m = 0; m < t.len; ++m) put(t.off + m, t.n1 > 0 ? (m / t.n1) * (m % t.n1) : m, t.len);
+        }
+    }
+    if (hipMalloc(dev, host.size() * sizeof(float2)) != hipSuccess) return WSFFT_ERROR_OUT_OF_MEMORY;
+    if (hipMemcpy(*dev, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(*dev);
+        *dev = nullptr;
+        return WSFFT_ERROR_HIP;
+    }
+    return WSFFT_SUCCESS;
 }
 
 // ---- autotuner -------------------------------------------------------------------
 // Each pass of a hot length has several compiled launch variants (radix plan,
-// tile width).  The choice per pass geometry is read from a cache file, and,
-// when tuning is requested (WSFFT_FLAG_TUNE or WSFFT_TUNE=1), measured at plan
+// tile width).  When tuning is requested (WSFFT_FLAG_TUNE or WSFFT_TUNE=1)
+// the choice per pass geometry is read from a cache file, or measured at plan
 // creation with HIP events on scratch buffers and appended to the cache.
+// Without a request the cache is read only if $WSFFT_TUNE_CACHE names it.
 // WSFFT_TUNE=0 disables both.  Cache: $WSFFT_TUNE_CACHE, else
 // $HOME/.cache/wsfft_tune.txt, one "key variant microseconds" line per entry.
 
@@ -380,6 +466,11 @@ void tune_plan(wsfft_plan_s* plan, bool requested) {
     const char* env = std::getenv("WSFFT_TUNE");
     if (env && std::strcmp(env, "0") == 0) return;
     requested = requested || (env && std::strcmp(env, "1") == 0);
+    // the cache is consulted only when tuning is requested or a cache file is
+    // named explicitly, so a plan made without either depends on its
+    // arguments alone, whatever earlier processes recorded
+    const char* named = std::getenv("WSFFT_TUNE_CACHE");
+    if (!requested && !(named && *named)) return;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, plan->device) != hipSuccess) return;
     const char* arch = prop.gcnArchName;
@@ -492,26 +583,8 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     std::vector<AxisGeo> order = split;   // split axes first: pass A reads the input
     order.insert(order.end(), direct.begin(), direct.end());
 
-    // twiddle tables, one per distinct (kind, length, n1):
-    //  kStage: the stage tables of the radix plans 0, 1, 2 of a pass length,
-    //          len entries each (stage_tw_offset); a pass uses the block of
-    //          its kernel's plan;
-    //  kPlain: entry m is W_len^m (inter-pass twiddles of strided split axes);
-    //  kMatrix: entry m is W_len^{(m div n1) * (m mod n1)}, the inter-pass
-    //          twiddle of output position k1 + n1*y2 of pass A of a
-    //          unit-stride split axis, so lanes that store consecutive outputs
-    //          read consecutive entries.
-    enum { kStage = 0, kPlain = 1, kMatrix = 2 };
-    struct Table { int kind; int64_t len, n1, off; };
-    std::vector<Table> tables;
-    int64_t tw_total = 0;
-    auto table_for = [&](int kind, int64_t len, int64_t n1 = 0) -> int64_t {
-        for (auto& t : tables)
-            if (t.kind == kind && t.len == len && t.n1 == n1) return t.off;
-        tables.push_back({kind, len, n1, tw_total});
-        tw_total += kind == kStage ? kTwPlans * len : len;
-        return tables.back().off;
-    };
+    TableSet ts;
+    auto table_for = [&](int kind, int64_t len, int64_t n1 = 0) { return ts.get(kind, len, n1); };
 
     const StorageKind kind = kind_of(dtype, flags);
     int S = 0;
@@ -585,16 +658,18 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
             P.src_sel = 2; P.dst_sel = 1;
         }
     }
-    // In-place calls: the first split axis goes through the work buffer too.
+    // In-place calls: the first split axis goes through the work buffer too
+    // (its pass A reads the whole input before any of it may be overwritten).
     for (size_t i = 0; i < plan->passes.size(); ++i) {
         Pass& P = plan->passes[i];
         P.src_sel_ip = P.src_sel;
         P.dst_sel_ip = P.dst_sel;
-        if (nsplit > 1 && i == 0 && P.four_step == 1) P.dst_sel_ip = 2;
-        if (nsplit > 1 && i == 1 && P.four_step == 2) P.src_sel_ip = 2;
+        if (nsplit > 0 && i == 0 && P.four_step == 1) P.dst_sel_ip = 2;
+        if (nsplit > 0 && i == 1 && P.four_step == 2) P.src_sel_ip = 2;
     }
+    plan->nsplit = nsplit;
     const int64_t N = nx * ny * nz;
-    if (nsplit > 1) plan->work_bytes = N * elem_bytes(dtype);
+    if (nsplit > 0) plan->work_bytes = N * elem_bytes(dtype);
 
     // ---- device ------------------------------------------------------------
     int ndev = 0;
@@ -605,37 +680,12 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     const bool tw32 = !half || (flags & WSFFT_FLAG_FP32_TWIDDLES);
     const int mant = tw32 ? 23 : (dtype == WSFFT_C16_FP16 ? 10 : 7);
     const int emin = tw32 ? -126 : (dtype == WSFFT_C16_FP16 ? -14 : -126);
-    std::vector<float2> host((size_t)std::max<int64_t>(tw_total, 1));
-    auto put = [&](int64_t at, int64_t m, int64_t len) {
-        double re, im;
-        root_fp64(m, len, &re, &im);
-        host[(size_t)at] = make_float2((float)round_to_format(re, mant, emin), (float)round_to_format(im, mant, emin));
-    };
-    for (auto& t : tables) {
-        if (t.kind == kStage) {
-            // entry (r-1)*Ns + k of stage s: W_{Ns*R}^{k*r} = W_len^{k*r*len/(Ns*R)}
-            for (int pl = 0; pl < kTwPlans; ++pl) {
-                const Radices rd = make_radices((int)t.len, pl);
-                const int64_t base = t.off + (int64_t)pl * t.len;
-                for (int st = 1; st < rd.n; ++st) {
-                    const int64_t R = rd.r[st], Ns = stage_ns(rd, st), tws = t.len / (Ns * R);
-                    const int64_t off = stage_tw_offset(rd, st);
-                    for (int64_t r = 1; r < R; ++r)
-                        for (int64_t k = 0; k < Ns; ++k) put(base + off + (r - 1) * Ns + k, k * r * tws, t.len);
-                }
-            }
-        } else {
-            for (int64_t m = 0; m < t.len; ++m) put(t.off + m, t.n1 > 0 ? (m / t.n1) * (m % t.n1) : m, t.len);
+    {
+        const wsfft_status_t st = upload_tables(ts, mant, emin, &plan->tw_dev);
+        if (st != WSFFT_SUCCESS) {
+            delete plan;
+            return fail(st);
         }
-    }
-    if (hipMalloc(&plan->tw_dev, host.size() * sizeof(float2)) != hipSuccess) {
-        delete plan;
-        return fail(WSFFT_ERROR_OUT_OF_MEMORY);
-    }
-    if (hipMemcpy(plan->tw_dev, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(plan->tw_dev);
-        delete plan;
-        return fail(WSFFT_ERROR_HIP);
     }
     if (plan->work_bytes > 0 && hipMalloc(&plan->work, (size_t)plan->work_bytes) != hipSuccess) {
         (void)hipFree(plan->tw_dev);
@@ -654,6 +704,7 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     }
     tune_plan(plan, (flags & WSFFT_FLAG_TUNE) != 0);
     describe_plan(plan);
+    log_plan(plan->desc);
     {
         std::lock_guard<std::mutex> g(g_plans_mu);
         g_plans.insert(plan);
@@ -664,6 +715,172 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
 
 wsfft_plan_t wsfft_plan_create(int64_t nx, int64_t ny, int64_t nz, wsfft_dtype_t dtype, int sign) {
     return wsfft_plan_create_ex(nx, ny, nz, dtype, sign, 0u);
+}
+
+// Real plans.  The forward transform of a real nx x ny x nz array keeps the
+// bins kx = 0 .. nx/2 (the rest follow by Hermitian symmetry): an x pass of
+// N = nx/2 complex points over the reals read in pairs, whose epilogue
+// recombines the even and odd halves into the N + 1 bins, then c2c passes
+// along y and z over the half spectrum (nx/2 + 1) x ny x nz.  The C2R
+// transform runs the z and y passes first, in place on its input, and the x
+// pass last, whose prologue undoes the recombination.
+wsfft_plan_t wsfft_plan_create_real(int64_t nx, int64_t ny, int64_t nz, unsigned flags) {
+    if (nx < 1 || ny < 1 || nz < 1) return fail(WSFFT_ERROR_INVALID_VALUE);
+    if (flags != 0u) return fail(WSFFT_ERROR_INVALID_VALUE);
+    const int64_t dims[3] = {nx, ny, nz};
+    for (int64_t d : dims)
+        if (d > WSFFT_MAX_AXIS || !is_smooth23(d)) return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+    if (nx % 2 != 0 || nx < 4 || nx / 2 > kMaxContigN) return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+    if (nx * ny > (int64_t(1) << 40) || nx * ny * nz > (int64_t(1) << 40)) return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+
+    wsfft_plan_s* plan = new (std::nothrow) wsfft_plan_s();
+    if (!plan) return fail(WSFFT_ERROR_OUT_OF_MEMORY);
+    plan->n[0] = nx; plan->n[1] = ny; plan->n[2] = nz;
+    plan->dtype = WSFFT_C64;
+    plan->sign = -1;
+    plan->flags = flags;
+    plan->real = true;
+    const int64_t N = nx / 2, nxh = N + 1;
+    TableSet ts;
+
+    // the x pass, both directions
+    Pass X{};
+    std::memset(&X.args, 0, sizeof X.args);
+    X.args.M = 1;
+    X.args.scale = 1.0f;
+    X.args.O1 = X.args.O2 = 1;
+    X.args.C = ny * nz;
+    X.args.es_in = X.args.es_out = 1;
+    X.args.cs_out = 1;
+    X.strided = false;
+    X.outer_dim = 0;
+    X.axis = 0;
+    X.n = N;
+    X.four_step = 0;
+    X.tw_off = ts.get(kStage, N);
+    X.tw4_off = ts.get(kHalf, nx);
+    X.pass_scale = X.inv_scale = 1.0f;
+    Pass XR = X, XC = X;
+    XR.args.os1_in = N;            // 2N reals as N complex
+    XR.args.os1_out = nxh;
+    XR.kern_neg = XR.kern_pos = find_real_c64_neg((int)N, false, kFusedR2C);
+    XC.args.os1_in = nxh;
+    XC.args.os1_out = N;
+    XC.kern_neg = XC.kern_pos = find_real_c64_pos((int)N, false, kFusedC2R);
+    if (!XR.kern_neg || !XC.kern_neg) { delete plan; return fail(WSFFT_ERROR_UNSUPPORTED_SIZE); }
+
+    // the y and z passes over the half spectrum, per axis: one direct pass or
+    // a four-step pair
+    std::vector<std::vector<Pass>> axes;
+    const AxisGeo geos[2] = {{1, ny, nxh, nz}, {2, nz, nxh * ny, 1}};
+    for (const AxisGeo& g : geos) {
+        if (g.n == 1) continue;
+        std::vector<Pass> ps;
+        if (direct_ok(g.n, true)) {
+            Pass P{};
+            set_direct(P, g);
+            P.axis = g.axis; P.n = g.n; P.four_step = 0;
+            P.tw_off = ts.get(kStage, g.n); P.tw4_off = -1;
+            ps.push_back(P);
+        } else {
+            int64_t n1, n2;
+            if (!split_axis(g.n, &n1, &n2)) { delete plan; return fail(WSFFT_ERROR_UNSUPPORTED_SIZE); }
+            Pass A{}, B{};
+            set_four_step(A, B, g, n1, n2);
+            A.axis = B.axis = g.axis;
+            A.n = n1; B.n = n2;
+            A.four_step = 1; B.four_step = 2;
+            A.tw_off = ts.get(kStage, n1); B.tw_off = ts.get(kStage, n2);
+            A.tw4_off = ts.get(kPlain, g.n);
+            B.tw4_off = -1;
+            ps.push_back(A);
+            ps.push_back(B);
+            ++plan->nsplit;
+        }
+        for (Pass& P : ps) {
+            P.pass_scale = P.inv_scale = 1.0f;
+            P.kern_neg = find_pass_kernel(kC64, -1, (int)P.n, true, P.four_step == 1);
+            P.kern_pos = find_pass_kernel(kC64, +1, (int)P.n, true, P.four_step == 1);
+            if (!P.kern_neg || !P.kern_pos) { delete plan; return fail(WSFFT_ERROR_UNSUPPORTED_SIZE); }
+            // a direct pass whose columns leave a ragged tile at every outer
+            // index runs its tiles on across the outer indices instead
+            PassArgs& a = P.args;
+            if (P.four_step == 0 && a.O1 > 1 && a.O2 == 1 && a.C % P.kern_neg->per_block != 0) {
+                a.flat_c = a.C;
+                a.C *= a.O1;
+                a.O1 = 1;
+            }
+        }
+        axes.push_back(ps);
+    }
+    // R2C: x (input -> output), then y, z in place on the output (a split
+    // axis through the work buffer); C2R: z, y in place on the input, then x
+    // (input -> output)
+    XR.src_sel = 0; XR.dst_sel = 1;
+    plan->passes.push_back(XR);
+    for (auto& ps : axes)
+        for (Pass P : ps) {
+            P.src_sel = P.four_step == 2 ? 2 : 1;
+            P.dst_sel = P.four_step == 1 ? 2 : 1;
+            plan->passes.push_back(P);
+        }
+    for (auto it = axes.rbegin(); it != axes.rend(); ++it)
+        for (Pass P : *it) {
+            P.src_sel = P.four_step == 2 ? 2 : 0;
+            P.dst_sel = P.four_step == 1 ? 2 : 0;
+            plan->cpasses.push_back(P);
+        }
+    XC.src_sel = 0; XC.dst_sel = 1;
+    plan->cpasses.push_back(XC);
+    // wsfft_execute_c2r_inverse: 1/N in the last pass
+    plan->cpasses.back().inv_scale = (float)(1.0 / ((double)nx * (double)ny * (double)nz));
+    for (auto* list : {&plan->passes, &plan->cpasses})
+        for (Pass& P : *list) {
+            P.src_sel_ip = P.src_sel;
+            P.dst_sel_ip = P.dst_sel;
+            const int64_t blocks = blocks_for(P, P.kern_neg);
+            if (blocks < 1 || blocks * P.kern_neg->threads > 0xffffffffLL) {
+                delete plan;
+                return fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+            }
+            P.grid = dim3((unsigned)blocks);
+        }
+    if (plan->nsplit > 0) plan->work_bytes = nxh * ny * nz * 8;
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { delete plan; return fail(WSFFT_ERROR_NO_DEVICE); }
+    if (hipGetDevice(&plan->device) != hipSuccess) { delete plan; return fail(WSFFT_ERROR_HIP); }
+    {
+        const wsfft_status_t st = upload_tables(ts, 23, -126, &plan->tw_dev);
+        if (st != WSFFT_SUCCESS) {
+            delete plan;
+            return fail(st);
+        }
+    }
+    if (plan->work_bytes > 0 && hipMalloc(&plan->work, (size_t)plan->work_bytes) != hipSuccess) {
+        (void)hipFree(plan->tw_dev);
+        delete plan;
+        return fail(WSFFT_ERROR_OUT_OF_MEMORY);
+    }
+    for (auto* list : {&plan->passes, &plan->cpasses})
+        for (Pass& P : *list) {
+            set_stage_tw(plan, P);
+            P.args.tw4 = P.tw4_off >= 0 ? plan->tw_dev + P.tw4_off : nullptr;
+            if (P.kern_neg->prepare() != hipSuccess || P.kern_pos->prepare() != hipSuccess) {
+                (void)hipFree(plan->tw_dev);
+                if (plan->work) (void)hipFree(plan->work);
+                delete plan;
+                return fail(WSFFT_ERROR_HIP);
+            }
+        }
+    describe_plan(plan);
+    log_plan(plan->desc);
+    {
+        std::lock_guard<std::mutex> g(g_plans_mu);
+        g_plans.insert(plan);
+    }
+    g_last_error = WSFFT_SUCCESS;
+    return plan;
 }
 
 int wsfft_plan_scale_log2(wsfft_plan_t plan) { return plan_live(plan) ? plan->scale_log2 : -1; }
@@ -704,23 +921,42 @@ namespace {
 // mode: 0 = plan sign, 1 = opposite sign (adjoint), 2 = opposite sign / N
 wsfft_status_t check_exec(const wsfft_plan_s* plan, const void* in, const void* out) {
     if (!plan_live(plan)) return WSFFT_ERROR_INVALID_PLAN;
+    if (plan->real) return WSFFT_ERROR_INVALID_VALUE;   // real plans run wsfft_execute_r2c / _c2r
     if (!in || !out) return WSFFT_ERROR_NULL_POINTER;
     const uintptr_t al = (uintptr_t)elem_bytes(plan->dtype);
     if (((uintptr_t)in % al) || ((uintptr_t)out % al)) return WSFFT_ERROR_MISALIGNED;
-    // a split axis reading the input cannot run in place without the work buffer
-    if (in == out && plan->work_bytes == 0)
-        for (const Pass& P : plan->passes)
-            if (P.four_step == 1 && P.src_sel == 0) return WSFFT_ERROR_INVALID_VALUE;
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
     if (cur != plan->device) return WSFFT_ERROR_WRONG_DEVICE;
     return WSFFT_SUCCESS;
 }
 
-// Enqueue pass index `pi` of a plan; returns false on a launch error.
+// Whether a call on these buffers goes through the plan's work buffer: always
+// with two split axes, and in place with one.
+bool uses_work(const wsfft_plan_s* plan, const void* in, const void* out) {
+    return plan->nsplit > 1 || (plan->nsplit == 1 && in == out);
+}
+
+// Arguments of a call on a real plan: in and out disjoint (identity checked),
+// aligned to their element sizes (real FP32: 4 bytes, complex64: 8).
+wsfft_status_t check_real(const wsfft_plan_s* plan, const void* in, const void* out, uintptr_t in_al,
+                          uintptr_t out_al) {
+    if (!plan_live(plan)) return WSFFT_ERROR_INVALID_PLAN;
+    if (!plan->real) return WSFFT_ERROR_INVALID_VALUE;
+    if (!in || !out) return WSFFT_ERROR_NULL_POINTER;
+    if (((uintptr_t)in % in_al) || ((uintptr_t)out % out_al)) return WSFFT_ERROR_MISALIGNED;
+    if (in == out) return WSFFT_ERROR_INVALID_VALUE;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
+    if (cur != plan->device) return WSFFT_ERROR_WRONG_DEVICE;
+    return WSFFT_SUCCESS;
+}
+
+// Enqueue pass index `pi` of a plan; returns false on a launch error.  Real
+// plans: the R2C passes in mode 0, the C2R passes otherwise.
 bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out, int mode,
                  hipStream_t stream, int64_t batch = 1) {
-    const Pass& P = plan->passes[pi];
+    const Pass& P = (plan->real && mode != 0) ? plan->cpasses[pi] : plan->passes[pi];
     PassArgs a = P.args;
     dim3 grid = P.grid;
     if (batch > 1) {   // `batch` arrays back to back: one more factor on the outermost count
@@ -847,12 +1083,50 @@ wsfft_status_t wsfft_execute_inverse(wsfft_plan_t plan, const void* in, void* ou
     return st != WSFFT_SUCCESS ? st : exec_plan(plan, in, out, 2, stream);
 }
 
+// The solve on a real plan, over the half spectrum in five passes: the R2C
+// x pass (f -> work), the forward y pass, one z pass that runs the forward
+// transform, the multiplier and the inverse transform of every z pencil, the
+// inverse y pass, and the C2R x pass (work -> u) with 1/N.
+static wsfft_status_t poisson_real(const wsfft_plan_s* plan, const float* f, float* u, void* work,
+                                   hipStream_t stream) {
+    using namespace wsfft;
+    const auto& ps = plan->passes;    // x (R2C), y, z
+    const auto& cs = plan->cpasses;   // z, y, x (C2R)
+    if (ps.size() != 3 || cs.size() != 3) return WSFFT_ERROR_UNSUPPORTED_SIZE;
+    if (ps[1].four_step != 0 || ps[2].four_step != 0 || ps[1].axis != 1 || ps[2].axis != 2 || cs[1].axis != 1)
+        return WSFFT_ERROR_UNSUPPORTED_SIZE;
+    const int64_t nx = plan->n[0], ny = plan->n[1], nz = plan->n[2], nxh = nx / 2 + 1;
+    const PassKernel* kz = find_real_c64_neg((int)nz, true, kFusedSolveZ);
+    if (!kz || nxh * ny > INT32_MAX) return WSFFT_ERROR_UNSUPPORTED_SIZE;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
+    if (cur != plan->device) return WSFFT_ERROR_WRONG_DEVICE;
+    if (kz->prepare() != hipSuccess) return WSFFT_ERROR_HIP;
+    auto go = [&](const Pass& P, const PassKernel* k, const void* src, void* dst, float scale) {
+        PassArgs a = P.args;
+        a.src = src;
+        a.dst = dst;
+        a.scale = scale;
+        a.tw = plan->tw_dev + P.tw_off + (int64_t)k->plan * P.n;   // the stage tables of k's radix plan
+        a.sym_nx = (int32_t)nxh;
+        a.sym_ny = (int32_t)ny;
+        a.sym_half = 1;
+        return k->launch(a, nullptr, dim3((unsigned)blocks_for(P, k)), stream) == hipSuccess;
+    };
+    const double N = (double)nx * (double)ny * (double)nz;
+    const bool ok = go(ps[0], ps[0].kern_neg, f, work, 1.0f) && go(ps[1], ps[1].kern_neg, work, work, 1.0f) &&
+                    go(ps[2], kz, work, work, 1.0f) && go(cs[1], cs[1].kern_pos, work, work, 1.0f) &&
+                    go(cs[2], cs[2].kern_pos, work, u, (float)(1.0 / N));
+    return ok ? WSFFT_SUCCESS : WSFFT_ERROR_HIP;
+}
+
 wsfft_status_t wsfft_poisson_solve(wsfft_plan_t plan, const float* f, float* u, void* work, hipStream_t stream) {
     using namespace wsfft;
     if (!plan_live(plan)) return WSFFT_ERROR_INVALID_PLAN;
     if (!f || !u || !work) return WSFFT_ERROR_NULL_POINTER;
     if (((uintptr_t)f % 4) || ((uintptr_t)u % 4) || ((uintptr_t)work % 8)) return WSFFT_ERROR_MISALIGNED;
     if (work == (const void*)f || work == (void*)u) return WSFFT_ERROR_INVALID_VALUE;
+    if (plan->real) return poisson_real(plan, f, u, work, stream);
     if (plan->dtype != WSFFT_C64) return WSFFT_ERROR_UNSUPPORTED_SIZE;
     // three direct passes x (contiguous), y, z (strided), each with fused kernels
     const auto& ps = plan->passes;
@@ -893,11 +1167,39 @@ wsfft_status_t wsfft_poisson_solve(wsfft_plan_t plan, const float* f, float* u, 
 
 wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const void* in, void* out,
                                   hipStream_t stream) {
-    const wsfft_status_t st = check_exec(plan, in, out);
+    const bool real = plan_live(plan) && plan->real;
+    const wsfft_status_t st = real ? check_real(plan, in, out, 4, 4) : check_exec(plan, in, out);
     if (st != WSFFT_SUCCESS) return st;
-    if (mode < 0 || mode > 2 || index < 0 || (size_t)index >= plan->passes.size()) return WSFFT_ERROR_INVALID_VALUE;
+    const size_t np = (real && mode != 0) ? plan->cpasses.size() : plan->passes.size();
+    if (mode < 0 || mode > 2 || index < 0 || (size_t)index >= np) return WSFFT_ERROR_INVALID_VALUE;
     return launch_pass(plan, (size_t)index, in, out, mode, stream) ? WSFFT_SUCCESS : WSFFT_ERROR_HIP;
 }
+
+wsfft_status_t wsfft_execute_r2c(wsfft_plan_t plan, const float* in, void* out, hipStream_t stream) {
+    const wsfft_status_t st = check_real(plan, in, out, 4, 8);
+    if (st != WSFFT_SUCCESS) return st;
+    for (size_t i = 0; i < plan->passes.size(); ++i)
+        if (!launch_pass(plan, i, in, out, 0, stream)) return WSFFT_ERROR_HIP;
+    return WSFFT_SUCCESS;
+}
+
+static wsfft_status_t exec_c2r(wsfft_plan_t plan, void* in, float* out, int mode, hipStream_t stream) {
+    const wsfft_status_t st = check_real(plan, in, out, 8, 4);
+    if (st != WSFFT_SUCCESS) return st;
+    for (size_t i = 0; i < plan->cpasses.size(); ++i)
+        if (!launch_pass(plan, i, in, out, mode, stream)) return WSFFT_ERROR_HIP;
+    return WSFFT_SUCCESS;
+}
+
+wsfft_status_t wsfft_execute_c2r(wsfft_plan_t plan, void* in, float* out, hipStream_t stream) {
+    return exec_c2r(plan, in, out, 1, stream);
+}
+
+wsfft_status_t wsfft_execute_c2r_inverse(wsfft_plan_t plan, void* in, float* out, hipStream_t stream) {
+    return exec_c2r(plan, in, out, 2, stream);
+}
+
+int wsfft_plan_is_real(wsfft_plan_t plan) { return plan_live(plan) ? (plan->real ? 1 : 0) : -1; }
 
 wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const void* const* in,
                                      void* const* out, int adjoint, hipStream_t stream) {
@@ -909,7 +1211,8 @@ wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const
         const wsfft_status_t st = check_exec(plans[i], in[i], out[i]);
         if (st != WSFFT_SUCCESS) return st;
         if (plans[i]->dtype != plans[0]->dtype) return WSFFT_ERROR_INVALID_VALUE;
-        if (plans[i]->work_bytes > 0) return WSFFT_ERROR_INVALID_VALUE;
+        // entries run pass-major, so a plan's work buffer would be shared
+        if (uses_work(plans[i], in[i], out[i])) return WSFFT_ERROR_INVALID_VALUE;
         maxp = std::max(maxp, plans[i]->passes.size());
     }
     const int mode = adjoint ? 1 : 0;
@@ -970,6 +1273,7 @@ struct wsfft_batch_plan_s {
     unsigned grid;
     wsfft::PersistPass* d_passes = nullptr;
     wsfft::PersistCounters* d_ctr = nullptr;
+    unsigned spin_limit = 1u << 22;   // polls before a dependency wait gives up
 };
 
 namespace {
@@ -1001,7 +1305,7 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
         const wsfft_status_t st = check_exec(plans[i], in[i], out[i]);
         if (st != WSFFT_SUCCESS) return batch_fail(st);
         const wsfft_plan_s* p = plans[i];
-        if (p->dtype != WSFFT_C64 || p->work_bytes > 0) return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
+        if (p->dtype != WSFFT_C64 || p->nsplit > 0) return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
         const int s = adjoint ? -p->sign : p->sign;
         if (sign == 0) sign = s;
         if (s != sign) return batch_fail(WSFFT_ERROR_INVALID_VALUE);
@@ -1088,12 +1392,19 @@ wsfft_status_t wsfft_batch_execute(wsfft_batch_plan_t b, hipStream_t stream) {
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
     if (cur != b->device) return WSFFT_ERROR_WRONG_DEVICE;
-    // a dependency wait gives up after 2^22 polls (well under a second per
-    // wait, far beyond any tile's duration): a bug cannot hang the GPU
-    return wsfft::persist_launch(b->sign, b->d_passes, b->npasses, b->levels, b->d_ctr, b->grid, 1u << 22, stream) ==
-                   hipSuccess
+    // a dependency wait gives up after spin_limit polls (by default 2^22, well
+    // under a second per wait and far beyond any tile's duration): a bug
+    // cannot hang the GPU
+    return wsfft::persist_launch(b->sign, b->d_passes, b->npasses, b->levels, b->d_ctr, b->grid, b->spin_limit,
+                                 stream) == hipSuccess
                ? WSFFT_SUCCESS
                : WSFFT_ERROR_HIP;
+}
+
+wsfft_status_t wsfft_batch_plan_set_spin_limit(wsfft_batch_plan_t b, unsigned polls) {
+    if (!batch_live(b)) return WSFFT_ERROR_INVALID_PLAN;
+    b->spin_limit = polls;
+    return WSFFT_SUCCESS;
 }
 
 int64_t wsfft_batch_plan_tiles(wsfft_batch_plan_t b) { return batch_live(b) ? b->total : -1; }
@@ -1101,9 +1412,16 @@ int64_t wsfft_batch_plan_tiles(wsfft_batch_plan_t b) { return batch_live(b) ? b-
 wsfft_status_t wsfft_batch_plan_check(wsfft_batch_plan_t b, int* timed_out) {
     if (!batch_live(b)) return WSFFT_ERROR_INVALID_PLAN;
     if (!timed_out) return WSFFT_ERROR_NULL_POINTER;
-    unsigned err = 0;
-    if (hipMemcpy(&err, &b->d_ctr->error, sizeof err, hipMemcpyDeviceToHost) != hipSuccess) return WSFFT_ERROR_HIP;
-    *timed_out = err != 0;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
+    if (cur != b->device) return WSFFT_ERROR_WRONG_DEVICE;
+    // launches already enqueued must have finished before their count is read
+    if (hipDeviceSynchronize() != hipSuccess) return WSFFT_ERROR_HIP;
+    unsigned failed = 0;
+    if (hipMemcpy(&failed, &b->d_ctr->failed, sizeof failed, hipMemcpyDeviceToHost) != hipSuccess)
+        return WSFFT_ERROR_HIP;
+    if (failed != 0 && hipMemset(&b->d_ctr->failed, 0, sizeof failed) != hipSuccess) return WSFFT_ERROR_HIP;
+    *timed_out = failed != 0;
     return WSFFT_SUCCESS;
 }
 

@@ -147,3 +147,38 @@ def test_status_strings(lib):
         assert lib.wsfft_status_string(s)
     assert lib.wsfft_status_string(OK) == b"success"
     assert lib.wsfft_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("dims,flags,want", [
+    ((0, 4, 4), 0, INVALID),
+    ((8, 8, 8), 1, INVALID),            # no flags are defined for real plans
+    ((9, 8, 8), 0, UNSUPPORTED),        # odd real axis
+    ((2, 8, 8), 0, UNSUPPORTED),        # nx < 4
+    ((65536, 1, 1), 0, UNSUPPORTED),    # nx/2 longer than one contiguous pass
+    ((10, 8, 8), 0, UNSUPPORTED),       # factor 5
+    ((8, 8, 7), 0, UNSUPPORTED),
+])
+def test_plan_create_real_rejects(lib, dims, flags, want):
+    f = lib.wsfft_plan_create_real
+    f.restype = ctypes.c_void_p
+    f.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_uint]
+    assert f(*dims, flags) is None
+    assert lib.wsfft_get_last_error() == want
+
+
+def test_real_calls_reject_invalid_plans(lib):
+    bogus = ctypes.c_void_p(0x1000)
+    for name in ("wsfft_execute_r2c", "wsfft_execute_c2r", "wsfft_execute_c2r_inverse"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_void_p] * 4
+        assert f(None, 0x1000, 0x2000, None) == BADPLAN
+        assert f(bogus, 0x1000, 0x2000, None) == BADPLAN
+    lib.wsfft_plan_is_real.argtypes = [ctypes.c_void_p]
+    assert lib.wsfft_plan_is_real(bogus) == -1
+
+
+def test_batch_spin_limit_rejects_invalid_plans(lib):
+    f = lib.wsfft_batch_plan_set_spin_limit
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint]
+    assert f(None, 5) == BADPLAN
+    assert f(ctypes.c_void_p(0x1000), 5) == BADPLAN

@@ -168,3 +168,30 @@ def test_batch_plan_rejects_unsupported(ws):
     with pytest.raises(ws.WsfftError) as ei:
         ws.BatchPlan([p1, p2], [y, y.clone()], [y.clone(), y.clone()])
     assert ei.value.status == 1
+
+
+def test_batch_plan_timeout_is_per_launch(ws):
+    """A launch whose dependency waits give up (forced from the host with a
+    spin limit of 0 polls: the launch still runs every tile and exits) is
+    reported by the check, and the next launch waits normally again and is
+    correct: the timeout record does not carry over into later launches."""
+    shapes = synth.batched_shapes(96, seed=3)
+    arrays = synth.batched_arrays(shapes, seed=3)
+    plans = [ws.Plan(nx, ny, nz, "c64", -1) for nx, ny, nz in shapes]
+    xs = [to_dev(a) for a in arrays]
+    ys = [torch.empty_like(x) for x in xs]
+    bp = ws.BatchPlan(plans, xs, ys)
+    bp.set_spin_limit(0)
+    bp.execute()
+    torch.cuda.synchronize()
+    assert bp.timed_out()          # thousands of first-level tiles are still in flight at the first wait
+    assert not bp.timed_out()      # the check clears the record
+    bp.set_spin_limit(1 << 22)
+    for y in ys:
+        y.fill_(0.0)
+    bp.execute()
+    torch.cuda.synchronize()
+    assert not bp.timed_out()
+    worst = max(rel_l2(to_host(y), oracle.fftn(a.astype(np.complex64).astype(np.complex128), -1))
+                for a, y in zip(arrays, ys))
+    assert worst <= TOL
