@@ -86,7 +86,8 @@ typedef enum {
     WSFFT_ERROR_NO_DEVICE = 6,        /* no visible HIP device */
     WSFFT_ERROR_HIP = 7,              /* a HIP runtime call failed (e.g. a launch) */
     WSFFT_ERROR_INVALID_PLAN = 8,     /* NULL, destroyed, or created on another device */
-    WSFFT_ERROR_WRONG_DEVICE = 9      /* current device differs from the plan's */
+    WSFFT_ERROR_WRONG_DEVICE = 9,     /* current device differs from the plan's */
+    WSFFT_ERROR_EXCEEDS_SCRATCH = 10  /* more work memory than the static scratch buffer holds */
 } wsfft_status_t;
 
 /* Plan flags for wsfft_plan_create_ex. */

@@ -61,6 +61,22 @@ wsfft_status_t wsfft_poisson_symbol(void* data, int64_t nx, int64_t ny, int64_t 
  * the same call. */
 wsfft_status_t wsfft_poisson_solve(wsfft_plan_t plan, const float* f, float* u, void* work, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same solve as
+ * wsfft_poisson_solve, with its work array taken from a static device buffer
+ * of the library instead of an argument.  The buffer holds 72 MiB
+ * (75497472 bytes) per GPU, from the library's load until the process ends:
+ * enough for a real plan with (nx/2+1)*ny*nz*8 bytes up to that (256^3:
+ * 64.5 MiB) or a complex plan with nx*ny*nz*8.  A larger grid returns
+ * WSFFT_ERROR_EXCEEDS_SCRATCH before any device work.  The call allocates
+ * nothing (the buffer's address on the current device is looked up once, at
+ * the first call on that device).  Every call on one GPU shares that GPU's
+ * buffer, which keeps the last call's contents (the solve needs no cleared
+ * memory): calls that overlap on one GPU -- on different streams, threads or
+ * processes' graphs replayed concurrently -- race and give wrong results.
+ * Other arguments, errors and results as wsfft_poisson_solve. */
+wsfft_status_t wsfft_poisson_solve_noalloc(wsfft_plan_t plan, const float* f, float* u, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

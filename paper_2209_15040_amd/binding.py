@@ -36,7 +36,7 @@ _TORCH_DTYPE = {C64: torch.complex64, C16_FP16: torch.float16, C16_BF16: torch.b
 STATUS = {
     0: "success", 1: "invalid value", 2: "unsupported size", 3: "null pointer",
     4: "misaligned pointer", 5: "out of device memory", 6: "no HIP device",
-    7: "HIP runtime error", 8: "invalid plan", 9: "wrong device",
+    7: "HIP runtime error", 8: "invalid plan", 9: "wrong device", 10: "exceeds the static scratch buffer",
 }
 
 
@@ -86,6 +86,7 @@ _real_to_complex = _sig("wsfft_real_to_complex", _int, [_vp, _vp, _i64, _vp])
 _complex_real_part = _sig("wsfft_complex_real_part", _int, [_vp, _vp, _i64, _vp])
 _poisson_symbol = _sig("wsfft_poisson_symbol", _int, [_vp, _i64, _i64, _i64, _vp])
 _poisson_solve = _sig("wsfft_poisson_solve", _int, [_vp, _vp, _vp, _vp, _vp])
+_poisson_solve_noalloc = _sig("wsfft_poisson_solve_noalloc", _int, [_vp, _vp, _vp, _vp])
 _plan_create_real = _sig("wsfft_plan_create_real", _vp, [_i64, _i64, _i64, ctypes.c_uint])
 _execute_r2c = _sig("wsfft_execute_r2c", _int, [_vp, _vp, _vp, _vp])
 _execute_c2r = _sig("wsfft_execute_c2r", _int, [_vp, _vp, _vp, _vp])

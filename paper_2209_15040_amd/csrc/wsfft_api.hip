@@ -543,6 +543,7 @@ const char* wsfft_status_string(wsfft_status_t st) {
         case WSFFT_ERROR_HIP: return "HIP runtime error";
         case WSFFT_ERROR_INVALID_PLAN: return "invalid plan";
         case WSFFT_ERROR_WRONG_DEVICE: return "current device is not the plan's device";
+        case WSFFT_ERROR_EXCEEDS_SCRATCH: return "work exceeds the library's static scratch buffer";
     }
     return "unknown status";
 }
@@ -1163,6 +1164,49 @@ wsfft_status_t wsfft_poisson_solve(wsfft_plan_t plan, const float* f, float* u, 
         go(ps[1], ps[1].kern_pos, work, work, ps[1].pass_scale) &&
         go(ps[2], kout, work, u, (float)((double)ps[2].pass_scale / N));
     return ok ? WSFFT_SUCCESS : WSFFT_ERROR_HIP;
+}
+
+}  // extern "C"
+
+// ---- allocation-free Poisson solve ------------------------------------------------
+// The work memory of wsfft_poisson_solve_noalloc: a file-scope device array
+// of kScratchBytes that every GPU running the library holds until the
+// process ends.  In host code its name is not a device address; each
+// device's address comes from hipGetSymbolAddress at the first call on that
+// device and is kept in g_scratch_ptr.
+namespace {
+constexpr size_t kScratchBytes = size_t(72) << 20;
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+extern "C" {
+
+wsfft_status_t wsfft_poisson_solve_noalloc(wsfft_plan_t plan, const float* f, float* u, hipStream_t stream) {
+    if (!plan_live(plan)) return WSFFT_ERROR_INVALID_PLAN;
+    if (!f || !u) return WSFFT_ERROR_NULL_POINTER;
+    if (((uintptr_t)f % 4) || ((uintptr_t)u % 4)) return WSFFT_ERROR_MISALIGNED;
+    const int64_t nx = plan->n[0], ny = plan->n[1], nz = plan->n[2];
+    const int64_t need = (plan->real ? nx / 2 + 1 : nx) * ny * nz * 8;
+    if (need > (int64_t)kScratchBytes) return WSFFT_ERROR_EXCEEDS_SCRATCH;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return WSFFT_ERROR_HIP;
+    if (cur != plan->device) return WSFFT_ERROR_WRONG_DEVICE;
+    if (cur < 0 || cur >= kScratchDevices) return WSFFT_ERROR_UNSUPPORTED_SIZE;
+    void* work = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (!g_scratch_ptr[cur]) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return WSFFT_ERROR_HIP;
+            g_scratch_ptr[cur] = p;
+        }
+        work = g_scratch_ptr[cur];
+    }
+    return wsfft_poisson_solve(plan, f, u, work, stream);
 }
 
 wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const void* in, void* out,
