@@ -5,11 +5,14 @@ Headline step: one 512^3 complex64 forward transform followed by its inverse
 (the paper times forward + inverse and reports half, Section 5), inputs
 already resident in HBM.  value = GFLOP/s by the 5 N log2 N count per
 transform.  Beside it: per-pass kernel times (HIP events on the launch
-stream) for the roofline of the dominant kernel, the 16-bit storage, batched,
-2D/1D and Poisson forward+backward variants, and the FP64 CPU oracle timed on
-the host cores.
+stream) for the roofline of the dominant kernel; the 16-bit storage, real
+(half-spectrum), batched, 2D/1D, 1024^3 and Poisson forward+backward
+variants; after all timing, the error of every timed result against the FP64
+oracle (`accuracy`); and the FP64 CPU oracle timed on the host cores on each
+workload (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-accuracy] [--variants a,b,...] [--no-variants]
 """
 from __future__ import annotations
 
@@ -254,6 +257,46 @@ def variant_cube1024(ws, torch, steps, warmup):
     return out
 
 
+def variant_real(ws, torch, steps, warmup):
+    """512^3 real FP32 (the real part of the headline draw): R2C forward then
+    the C2R inverse (1/N), per transform; the half spectrum halves the bytes
+    of every pass."""
+    import synth
+    n = 512
+    N = n ** 3
+    log("variant real 512^3: R2C + C2R inverse")
+    a = synth.normal_c64((n, n, n), seed=1).real.copy()
+    x = torch.from_numpy(a).cuda()
+    del a
+    plan = ws.RealPlan(n, n, n)
+    H = torch.empty((n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    r = torch.empty_like(x)
+
+    def step():
+        plan.r2c(x, H)
+        plan.c2r(H, r, inverse=True)
+
+    ms, per = time_events(step, steps, warmup)
+    fwd_ms, _ = time_events(lambda: plan.r2c(x, H), steps, warmup)
+    passes = []
+    for i in range(plan.num_passes):
+        pm, _ = time_events(lambda i=i: plan.execute_pass(i, x, H, 0), steps, warmup)
+        passes.append(pm)
+    half = (n // 2 + 1) * n * n
+    # bytes per R2C: x pass reads N FP32 and writes the half spectrum; y and z
+    # read and write the half spectrum; the C2R mirrors it
+    byts = N * 4 + 5 * half * 8
+    del x, H, r
+    torch.cuda.empty_cache()
+    us = ms * 1e3 / 2
+    return {"plan": plan.describe(), "us_per_transform": us, "us_r2c": fwd_ms * 1e3,
+            "GFLOPs_c2c_equivalent": flops(N) / (us * 1e-6) / 1e9,
+            "bytes_per_transform": byts, "bytes_c2c_transform": 6 * N * 8,
+            "hbm_frac": byts / (us * 1e-6) / HBM_PEAK, "r2c_pass_ms": passes,
+            "note": "GFLOP/s counts the complex 5 N log2 N of the same grid, as a real transform's "
+                    "equivalent rate"}
+
+
 def variant_poisson(ws, torch, steps, warmup):
     import synth
     n = 256
@@ -261,76 +304,253 @@ def variant_poisson(ws, torch, steps, warmup):
     f = torch.from_numpy(synth.gaussian_bumps(n, 64, 0.05, seed=4).astype(np.float32)).cuda()
     w = torch.from_numpy(synth.poisson_weights(n, seed=4).astype(np.float32)).cuda()
 
-    def fwd(fused=True):
-        return (ws.poisson_solve(f, fused=fused) * w).sum()
+    def fwd(path):
+        return (ws.poisson_solve(f, path=path) * w).sum()
 
-    def fwd_bwd(fused=True):
+    def fwd_bwd(path):
         fg = f.detach().requires_grad_(True)
-        loss = (ws.poisson_solve(fg, fused=fused) * w).sum()
+        loss = (ws.poisson_solve(fg, path=path) * w).sum()
         loss.backward()
         return fg.grad
 
-    with torch.no_grad():
-        ms_f, _ = time_events(fwd, steps, warmup)
-        ms_f_c, _ = time_events(lambda: fwd(False), steps, warmup)
-    ms_fb, _ = time_events(fwd_bwd, steps, warmup)
-    ms_fb_c, _ = time_events(lambda: fwd_bwd(False), steps, warmup)
+    out = {}
+    for path in ("real", "complex", "composed"):
+        with torch.no_grad():
+            out[f"ms_forward_{path}"], _ = time_events(lambda: fwd(path), steps, warmup)
+        out[f"ms_forward_backward_{path}"], _ = time_events(lambda: fwd_bwd(path), steps, warmup)
     plan = ws.get_plan(torch.empty((n, n, n), dtype=torch.complex64, device="cuda"), -1)
     x = torch.empty((n, n, n), dtype=torch.complex64, device="cuda")
     y = torch.empty_like(x)
     ms_fft, _ = time_events(lambda: plan.execute(x, y), steps, warmup)
-    return {"ms_forward": ms_f, "ms_forward_backward": ms_fb, "ms_plain_fft_256": ms_fft,
-            "ms_forward_composed": ms_f_c, "ms_forward_backward_composed": ms_fb_c,
-            "ffts_forward": 2, "ffts_forward_backward": 4,
-            "note": "forward = loss (u*w).sum() with the fused six-pass solve; composed = the plan's "
-                    "transforms plus separate elementwise kernels"}
+    out.update({"ms_forward": out["ms_forward_real"], "ms_forward_backward": out["ms_forward_backward_real"],
+                "ms_plain_fft_256": ms_fft, "ffts_forward": 2, "ffts_forward_backward": 4,
+                "note": "forward = loss (u*w).sum(); real = the five-pass half-spectrum solve (default), "
+                        "complex = the six-pass complex solve, composed = the complex plan's transforms plus "
+                        "separate elementwise kernels; backward = the same solve on the gradient"})
+    return out
 
 
-def cpu_baseline():
+def rel_l2(a, b) -> float:
+    """||a - b|| / ||b|| over all re and im components, in FP64."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    d = np.linalg.norm((a.astype(np.complex128) if np.iscomplexobj(a) else a.astype(np.float64))
+                       - (b.astype(np.complex128) if np.iscomplexobj(b) else b.astype(np.float64)))
+    nb = np.linalg.norm(b)
+    return float(d / (nb if nb > 0 else 1.0))
+
+
+def _host(t, torch):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _c16_host(t, kind, torch) -> np.ndarray:
+    """(..., 2) float16 / bfloat16 device tensor to complex128 (exact)."""
+    torch.cuda.synchronize()
+    if kind == "fp16":
+        p = t.cpu().numpy().astype(np.float64)
+    else:
+        p = t.cpu().view(torch.int16).numpy().view(np.uint16)
+        p = (p.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return p[..., 0] + 1j * p[..., 1]
+
+
+def accuracy(ws, torch, variants) -> dict:
+    """Error of each timed result against the FP64 oracle, computed after all
+    timing on the same seeded inputs: one untimed run of the GPU path, its
+    output copied to the host.  Bounds: relative L2 1e-6 for FP32 data
+    (round trips 2e-6), 3e-3 for 16-bit storage; BF16 with BF16 twiddles is
+    reported against 3e-3 and against its derived bound of 3 one-rounding
+    floors (the floor: rounding the exact result once to the storage type)."""
     import oracle
     import synth
+    out = {}
     n = 512
     N = n ** 3
-    threads = oracle.default_threads()
-    a = synth.normal_c64((n, n, n), seed=1).astype(np.complex128)
-    # round trips until at least 10 s of CPU time have run (at most 10)
-    reps, fwd_s, total = 0, 0.0, 0.0
-    while reps < 10 and (reps == 0 or total < 10.0):
-        t0 = time.perf_counter()
-        X = oracle.fftn(a, -1, threads)
-        t1 = time.perf_counter()
-        oracle.fftn(X, +1, threads)
-        t2 = time.perf_counter()
-        fwd_s += t1 - t0
-        total += t2 - t0
-        reps += 1
-    secs = total / (2 * reps)
-    # the same oracle on one core: one 256^3 forward transform (a 512^3 one
-    # takes most of a minute there)
-    n1 = 256
-    a1 = np.ascontiguousarray(a[:n1, :n1, :n1])
-    t0 = time.perf_counter()
-    oracle.fftn(a1, -1, 1)
-    one_core_s = time.perf_counter() - t0
-    cpu = "unknown"
+
+    log("accuracy: 512^3 complex64 forward and round trip vs the FP64 oracle")
+    a = synth.normal_c64((n, n, n), seed=1)
+    plan = ws.Plan(n, n, n, "c64", -1)
+    x = torch.from_numpy(a).cuda()
+    y = plan.execute(x)
+    r = plan.execute_inverse(y)
+    yh, rh = _host(y, torch), _host(r, torch)
+    del x, y, r
+    torch.cuda.empty_cache()
+    X = oracle.fftn(a, -1)
+    out["c64_512_forward"] = {"rel_l2": rel_l2(yh, X), "bound": 1e-6}
+    del yh
+    out["c64_512_round_trip"] = {"rel_l2": rel_l2(rh, a), "bound": 2e-6}
+    del rh
+
+    if "real_512" in variants:
+        log("accuracy: 512^3 real R2C and round trip")
+        ar = a.real.copy()
+        rp = ws.RealPlan(n, n, n)
+        xr = torch.from_numpy(ar).cuda()
+        H = rp.r2c(xr)
+        Hh = _host(H, torch)
+        back = _host(rp.c2r(H, inverse=True), torch)
+        del xr, H
+        torch.cuda.empty_cache()
+        Xr = oracle.rfftn(ar)
+        out["real_512_r2c"] = {"rel_l2": rel_l2(Hh, Xr), "bound": 1e-6}
+        out["real_512_round_trip"] = {"rel_l2": rel_l2(back, ar), "bound": 2e-6}
+        del Hh, Xr, back, ar
+    del a, X
+
+    kinds = [(k, f) for k, f, v in (("fp16", 0, "fp16"), ("fp16", ws.FLAG_FP16_MATH, "fp16_math"),
+                                    ("bf16", 0, "bf16"), ("bf16", ws.FLAG_FP32_TWIDDLES, "bf16_fp32_twiddles"))
+             if v in variants]
+    for kind in ("fp16", "bf16"):
+        mine = [(k, f) for k, f in kinds if k == kind]
+        if not mine:
+            continue
+        log(f"accuracy: 512^3 {kind} storage")
+        z = synth.normal_c64((n, n, n), seed=2)
+        z *= 0.5
+        xf = torch.from_numpy(z.view(np.float32).reshape(n, n, n, 2)).cuda()
+        del z
+        x = xf.to(torch.float16 if kind == "fp16" else torch.bfloat16)   # nearest even
+        del xf
+        a16 = _c16_host(x, kind, torch)
+        X = oracle.fftn(a16, -1)
+        del a16
+        # the one-rounding floor of this storage type at the plan's scale
+        S = 15
+        Xs = (X * 2.0 ** -S).astype(np.complex64)
+        t = torch.from_numpy(Xs.view(np.float32).reshape(n, n, n, 2)).to(
+            torch.float16 if kind == "fp16" else torch.bfloat16)
+        del Xs
+        floor = rel_l2(_c16_host(t, kind, torch) * 2.0 ** S, X)
+        del t
+        for k, f in mine:
+            p = ws.Plan(n, n, n, k, -1, f)
+            got = _c16_host(p.execute(x), k, torch) * 2.0 ** p.scale_log2
+            torch.cuda.empty_cache()
+            name = {0: kind, ws.FLAG_FP16_MATH: "fp16_math", ws.FLAG_FP32_TWIDDLES: "bf16_fp32_twiddles"}[f]
+            e = rel_l2(got, X)
+            del got
+            rec = {"rel_l2": e, "bound": 3e-3, "floor": floor, "floors": e / floor, "within_bound": e <= 3e-3}
+            if kind == "bf16" and f == 0:
+                rec["derived_bound"] = 3 * floor
+                rec["note"] = "BF16 twiddles (the workload's literal recipe): over the 3e-3 target"
+            out[name + "_512_forward"] = rec
+        del x, X
+        torch.cuda.empty_cache()
+
+    if "batched_96" in variants:
+        log("accuracy: 96 uneven arrays, merged launches and the persistent launch")
+        shapes = synth.batched_shapes(96, seed=3)
+        arrays = [a.astype(np.complex64) for a in synth.batched_arrays(shapes, seed=3)]
+        plans = [ws.Plan(nx, ny, nz, "c64", -1) for nx, ny, nz in shapes]
+        xs = [torch.from_numpy(a).cuda() for a in arrays]
+        ys = [torch.empty_like(x) for x in xs]
+        zs = [torch.empty_like(x) for x in xs]
+        ws.execute_batched(plans, xs, ys)
+        bp = ws.BatchPlan(plans, xs, zs)
+        bp.execute()
+        worst_m = worst_p = 0.0
+        for a, y, z in zip(arrays, ys, zs):
+            want = oracle.fftn(a.astype(np.complex128), -1)
+            worst_m = max(worst_m, rel_l2(_host(y, torch), want))
+            worst_p = max(worst_p, rel_l2(_host(z, torch), want))
+        out["batched_96_worst"] = {"rel_l2": worst_m, "bound": 1e-6}
+        out["batched_96_persistent_worst"] = {"rel_l2": worst_p, "bound": 1e-6, "timed_out": bp.timed_out()}
+        bp.close()
+        del xs, ys, zs
+        torch.cuda.empty_cache()
+
+    if "poisson_256" in variants:
+        log("accuracy: Poisson 256^3 u and gradient")
+        m = 256
+        f = synth.gaussian_bumps(m, 64, 0.05, seed=4).astype(np.float32)
+        w = synth.poisson_weights(m, seed=4).astype(np.float32)
+        u_ref = oracle.poisson_apply(f.astype(np.float64))
+        g_ref = oracle.poisson_loss_grad(w.astype(np.float64))
+        wt = torch.from_numpy(w).cuda()
+        for path in ("real", "complex", "composed"):
+            fg = torch.from_numpy(f).cuda().requires_grad_(True)
+            u = ws.poisson_solve(fg, path=path)
+            (u * wt).sum().backward()
+            out[f"poisson_256_{path}"] = {"u_rel_l2": rel_l2(_host(u, torch), u_ref),
+                                          "grad_rel_l2": rel_l2(_host(fg.grad, torch), g_ref), "bound": 1e-6}
+        del wt
+        torch.cuda.empty_cache()
+    return out
+
+
+def _cpu_name() -> str:
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
+    return "unknown"
+
+
+def _median3(fn) -> float:
+    t = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        fn()
+        t.append(time.perf_counter() - t0)
+    return statistics.median(t)
+
+
+def cpu_baseline(one_core: bool = True) -> dict:
+    """The FP64 oracle on the host cores, timed around the transforms only
+    (inputs drawn beforehand), median of 3, on every workload; the 512^3
+    forward also on one core."""
+    import oracle
+    import synth
+    threads = oracle.default_threads()
+    n = 512
+    N = n ** 3
+    log(f"cpu baseline: 512^3 round trip, {threads} threads")
+    a = synth.normal_c64((n, n, n), seed=1).astype(np.complex128)
+    t_rt = _median3(lambda: oracle.fftn(oracle.fftn(a, -1, threads), +1, threads))
+    secs = t_rt / 2
+    work = {"512cubed_forward_inverse": {"s_per_transform": secs, "GFLOPs": flops(N) / secs / 1e9}}
+    if one_core:
+        log("cpu baseline: 512^3 forward on one core")
+        t1 = _median3(lambda: oracle.fftn(a, -1, 1))
+        work["512cubed_forward_one_core"] = {"s": t1, "GFLOPs": flops(N) / t1 / 1e9, "cores": 1}
+    del a
+    log("cpu baseline: 32^3, 8192^2, 1024 x 65536")
+    a = synth.uniform_c((32, 32, 32), seed=0)
+    t = _median3(lambda: oracle.fftn(a, -1, threads))
+    work["32cubed_forward"] = {"s": t, "GFLOPs": flops(32 ** 3) / t / 1e9}
+    a = synth.normal_c64((8192, 8192), seed=1).astype(np.complex128)
+    t = _median3(lambda: oracle.fftn(a, -1, threads))
+    work["2d_8192_forward"] = {"s": t, "GFLOPs": flops(8192 ** 2) / t / 1e9}
+    a = a.reshape(1024, 65536)
+    t = _median3(lambda: oracle.fft1d_batch(a, -1, threads))
+    work["1d_65536_x1024_forward"] = {"s": t, "GFLOPs": 1024 * flops(65536) / t / 1e9}
+    del a
+    log("cpu baseline: 96 uneven arrays")
+    shapes = synth.batched_shapes(96, seed=3)
+    arrays = synth.batched_arrays(shapes, seed=3)
+    t = _median3(lambda: [oracle.fftn(b, -1, threads) for b in arrays])
+    work["batched_96_forward"] = {"s": t, "GFLOPs": sum(flops(b.size) for b in arrays) / t / 1e9}
+    del arrays
+    log("cpu baseline: Poisson 256^3")
+    f = synth.gaussian_bumps(256, 64, 0.05, seed=4)
+    w = synth.poisson_weights(256, seed=4)
+    t = _median3(lambda: oracle.poisson_apply(f, threads))
+    work["poisson_256_forward"] = {"s": t, "ffts": 2}
+    t = _median3(lambda: oracle.poisson_loss_grad(w, threads))
+    work["poisson_256_gradient"] = {"s": t, "ffts": 2}
     return {"value": flops(N) / secs / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} x the 512^3 forward+inverse round trip (the headline step), FP64 C oracle, "
-                      f"{threads} threads, {total:.1f} s in all; {secs * 1e3:.0f} ms per transform "
-                      f"(forward {fwd_s / reps:.2f} s); cpu: {cpu}",
-            "one_core": {"value": flops(n1 ** 3) / one_core_s / 1e9, "unit": "GFLOP/s", "cores": 1,
-                         "sample": f"one 256^3 forward transform (a corner of the same input), 1 thread, "
-                                   f"{one_core_s:.1f} s"}}
+            "sample": f"median of 3 x the 512^3 forward+inverse round trip (the headline step), FP64 C oracle, "
+                      f"{threads} threads: {secs * 1e3:.0f} ms per transform; cpu: {_cpu_name()}",
+            "workloads": work}
 
 
-VARIANTS = ["fp16", "bf16", "bf16_fp32_twiddles", "fp16_math", "batched_96", "2d_8192", "1d_65536_x1024",
-            "32cubed", "1024cubed", "poisson_256"]
+VARIANTS = ["fp16", "bf16", "bf16_fp32_twiddles", "fp16_math", "real_512", "batched_96", "2d_8192",
+            "1d_65536_x1024", "32cubed", "1024cubed", "poisson_256"]
 
 
 def main() -> int:
@@ -339,6 +559,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the error check against the oracle")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--variants", default="", help="comma-separated subset of the variants (default: all)")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -396,6 +617,7 @@ def main() -> int:
             "bf16": lambda: variant_c16(ws, torch, "bf16", vs, 2),
             "bf16_fp32_twiddles": lambda: variant_c16(ws, torch, "bf16", vs, 2, ws.FLAG_FP32_TWIDDLES),
             "fp16_math": lambda: variant_c16(ws, torch, "fp16", vs, 2, ws.FLAG_FP16_MATH),
+            "real_512": lambda: variant_real(ws, torch, vs, 2),
             "batched_96": lambda: variant_batched(ws, torch, vs, 2),
             "2d_8192": lambda: variant_rank(ws, torch, (8192, 8192, 1), vs, 2),
             "1d_65536_x1024": lambda: variant_rank(ws, torch, (65536, 1, 1), vs, 2, batch=1024),
@@ -406,9 +628,11 @@ def main() -> int:
         assert list(runs) == VARIANTS
         for name in only:
             variants[name] = runs[name]()
+    acc = None
+    if not args.no_accuracy:
+        acc = accuracy(ws, torch, list(variants))
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: FP64 oracle, 512^3 round trip")
         cpu = cpu_baseline()
     out = {
         "metric": METRIC,
@@ -433,6 +657,7 @@ def main() -> int:
         "passes": head["passes"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "accuracy": acc,
         "variants": variants,
     }
     print(json.dumps(out), flush=True)

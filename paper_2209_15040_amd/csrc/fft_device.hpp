@@ -595,6 +595,9 @@ enum : int {
                             // reals as N complex pairs, stored at q*os1_out
     kFlagSolveZ = 1024,     // strided layout, z pass of a Poisson solve: forward FFT, times
                             // -1/|k|^2, inverse FFT (opposite sign) of each pencil in one tile
+    kFlagTemporalStore = 2048,  // with kFlagNontemporal: streaming loads but ordinary (cached)
+                                // stores, so partial lines written by neighbouring accesses merge
+                                // in the cache before they reach memory
 };
 
 // -------------------------------------------------------------- pass args ---
@@ -621,7 +624,7 @@ struct PassArgs {
     int32_t sym_nx;       // kFlagPoisson / kFlagSolveZ: column c of the z pass is
     int32_t sym_ny;       //   (x, y) = (c mod sym_nx, c div sym_nx)
     int32_t sym_half;     //   nonzero: the columns are a half spectrum, kx = x (else the wavenumber of x)
-    int32_t pad_;
+    int32_t xcd_order;    // nonzero: each XCD takes a contiguous range of tiles (see xcd_tile)
     // strided layout: nonzero flattens the columns over (column, o1) pairs:
     // C counts flat_c * (the original O1) columns, column i is original column
     // i mod flat_c of outer index i div flat_c (O1 = 1), so tiles run on across
@@ -646,6 +649,18 @@ struct BatchTable {
     int32_t pad;
     ArrayDesc d[kMaxBatchDescs];
 };
+
+// Workgroups are dispatched to the 8 XCDs of the chip in turn (workgroup b
+// to XCD b mod 8), and each XCD has its own L2.  This maps workgroup b to a
+// tile so that XCD x works through the contiguous range of tiles
+// [x*q + min(x, r), ...) (q = blocks / 8, r = blocks mod 8), in order: tiles
+// that share cache lines (neighbouring columns of rows that are not
+// line-aligned) then meet in one L2.  A bijection on [0, blocks).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(unsigned b, unsigned blocks) {
+    const unsigned x = b % kXcds, i = b / kXcds, q = blocks / kXcds, r = blocks % kXcds;
+    return (int64_t)x * q + (x < r ? x : r) + i;
+}
 
 // Per-thread context of one tile.  Besides the element indices, the split
 // form of the addresses: element e of this thread's pencil or column is at
@@ -687,6 +702,7 @@ struct PencilPass {
     static constexpr bool SCALE_IN = IO::scale_at_load;
     static_assert(N % K == 0, "K must divide N");
     static constexpr bool NT = (FLAGS & kFlagNontemporal) != 0;
+    static constexpr bool NTS = NT && (FLAGS & kFlagTemporalStore) == 0;   // streaming stores
     static constexpr bool FOURSTEP = (FLAGS & kFlagFourStep) != 0;
     static constexpr bool REALIN = (FLAGS & kFlagRealIn) != 0;
     static constexpr bool REALOUT = (FLAGS & kFlagRealOut) != 0;
@@ -707,7 +723,7 @@ struct PencilPass {
         else return IO::load(p, i);
     }
     __device__ __forceinline__ static void gstore(void* p, int64_t i, V v) {
-        if constexpr (NT) IO::store_nt(p, i, v);
+        if constexpr (NTS) IO::store_nt(p, i, v);
         else IO::store(p, i, v);
     }
     // first-pass input and last-pass output, real where the fused flags say so
@@ -725,7 +741,7 @@ struct PencilPass {
     }
     __device__ __forceinline__ static void st_out(char* b, uint32_t off, V v) {
         if constexpr (REALOUT) __builtin_nontemporal_store(v.x, gstore_at<float>(b, off));
-        else IO::template st<NT>(b, off, v);
+        else IO::template st<NTS>(b, off, v);
     }
     static constexpr Radices RD = make_radices(N, PLAN);
     static constexpr int NS = RD.n;
@@ -1110,7 +1126,7 @@ struct PencilPass {
                     if (col >= a.C) continue;
                     V x = lds[lidx(pl, el)];
                     if (FOURSTEP && a.tw4_mode != 0) x = cmul(x, w4[i]);
-                    if (fit) IO::template st<NT>(obase, (uint32_t)pl * cs32 + (uint32_t)e * es32, oscale(x, a));
+                    if (fit) IO::template st<NTS>(obase, (uint32_t)pl * cs32 + (uint32_t)e * es32, oscale(x, a));
                     else gstore(a.dst, b0 + pl * a.cs_out + (int64_t)e * a.es_out, oscale(x, a));
                 }
             }
@@ -1143,7 +1159,7 @@ struct PencilPass {
             return;
         }
         if (c.split) {
-            if constexpr (pairable<S>()) {
+            if constexpr (pairable_store<S>()) {
                 if (((reinterpret_cast<uintptr_t>(c.ob) + c.ol) & (2 * IO::bytes - 1)) == 0) {
 #pragma unroll
                     for (int t = 0; t < Q::NB; t += 2)
@@ -1166,7 +1182,7 @@ struct PencilPass {
             }
             return;
         }
-        if constexpr (pairable<S>()) {
+        if constexpr (pairable_store<S>()) {
             if (pair_aligned(a.dst, c.base_out)) {
 #pragma unroll
                 for (int t = 0; t < Q::NB; t += 2) {
@@ -1285,6 +1301,8 @@ struct PencilPass {
     template <int S> static constexpr bool pairable() {
         return PAIRS && NT && St<S>::FULL && St<S>::NB % 2 == 0 && St<S>::NBF % 2 == 0;
     }
+    // the paired stores are streaming stores
+    template <int S> static constexpr bool pairable_store() { return pairable<S>() && NTS; }
     __device__ __forceinline__ static bool pair_aligned(const void* p, int64_t base) {
         return ((reinterpret_cast<uintptr_t>(p) & (2 * IO::bytes - 1)) == 0) && (base % 2 == 0);
     }
@@ -1374,7 +1392,7 @@ struct PencilPass {
         // A merged batch launch first picks its array; both kinds of launch
         // then share one pipeline.
         PassArgs a = a0;
-        int64_t t = blockIdx.x;
+        int64_t t = a0.xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
         if (bt.count != 0) {
             int i = 0;
             while (i + 1 < bt.count && t >= bt.d[i].tile_end) ++i;

@@ -22,12 +22,14 @@ struct PassKernel {
     hipError_t (*prepare)();   // one-time function attributes
     int fused;          // 0: plain pass; complex64 only: Poisson solve passes
                         // 1 real input, 2 times -1/|k|^2, 3 real output;
-                        // 4 R2C x pass, 5 C2R x pass, 6 fused solve z pass
+                        // 4 R2C x pass, 5 C2R x pass, 6 fused solve z pass,
+                        // 7 strided pass with cached loads and stores
 };
 
 enum FusedKind {
     kFusedNone = 0, kFusedRealIn = 1, kFusedPoisson = 2, kFusedRealOut = 3,
-    kFusedR2C = 4, kFusedC2R = 5, kFusedSolveZ = 6
+    kFusedR2C = 4, kFusedC2R = 5, kFusedSolveZ = 6,
+    kFusedCached = 7   // a plain strided pass with cached (not streaming) loads and stores
 };
 
 // NULL when no kernel of that length/layout/variant exists.
