@@ -100,6 +100,11 @@ typedef enum {
  * without the flag) and every arithmetic step rounds to FP16.  Twiddles are
  * FP16 whatever WSFFT_FLAG_FP32_TWIDDLES says. */
 #define WSFFT_FLAG_FP16_MATH 4u
+/* WSFFT_C64 plans whose x and y axes each take one pass and whose xy-plane
+ * holds at most 8192 values (axes of 32 .. 256 points) fuse the x and y
+ * supersteps into one pass over whole planes in LDS (two HBM round trips
+ * for a 3D array instead of three).  This flag keeps them separate. */
+#define WSFFT_FLAG_NO_PLANE 8u
 
 /*
  * Autotuning.  Passes of the hot lengths (powers of two up to 1024 strided,

@@ -49,7 +49,8 @@ wsfft_status_t wsfft_poisson_symbol(void* data, int64_t nx, int64_t ny, int64_t 
  * the first forward pass reads the real input, the last forward pass
  * applies the multiplier as it stores, and the last inverse pass stores only
  * the real part.  work: nx*ny*nz complex64.  Every axis needs a fused kernel
- * (32, 64, 128, 256, 512 or 1024 points).
+ * (32, 64, 128, 256, 512 or 1024 points) and a pass of its own: a plan with
+ * a fused xy-plane pass (see WSFFT_FLAG_NO_PLANE) is unsupported.
  *
  * f, u: nx*ny*nz FP32 device arrays (x fastest, 4-byte aligned; f and u may
  * be the same array).  work: caller-owned, 8-byte aligned, disjoint from f

@@ -30,6 +30,7 @@ C64, C16_FP16, C16_BF16 = 0, 1, 2
 FLAG_FP32_TWIDDLES = 1
 FLAG_TUNE = 2
 FLAG_FP16_MATH = 4       # FP16 plans: packed FP16 butterfly arithmetic
+FLAG_NO_PLANE = 8        # complex64 plans: keep the x and y passes separate (no fused plane pass)
 DTYPES = {"c64": C64, "fp16": C16_FP16, "bf16": C16_BF16}
 _TORCH_DTYPE = {C64: torch.complex64, C16_FP16: torch.float16, C16_BF16: torch.bfloat16}
 
@@ -568,7 +569,8 @@ def _poisson_fused(f: torch.Tensor, path: str):
         plan = _cached_real_plan(xyz, f.device)
         wshape = (xyz[2], xyz[1], xyz[0] // 2 + 1)
     else:
-        plan = _cached_plan(xyz, C64, -1, 0, f.device)
+        # the six-pass complex solve needs separate x and y passes
+        plan = _cached_plan(xyz, C64, -1, FLAG_NO_PLANE, f.device)
         wshape = tuple(f.shape)
     u = torch.empty_like(f)
     st_h = _stream(None)

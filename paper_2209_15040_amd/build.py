@@ -79,12 +79,60 @@ def build(incremental: bool = False, jobs: int | None = None) -> str:
     return LIB
 
 
+# Host-side sanitizer build for the CPU tests of the C-ABI: the units with host
+# logic (argument checks, plans, schedules, the batch and pointwise entry
+# points) recompiled with AddressSanitizer and UndefinedBehaviorSanitizer on
+# their host code only, linked with the kernel units of the regular build.
+# Run its users with the ASan runtime preloaded (asan_runtime()).
+SANITIZED_UNITS = ["wsfft_api.hip", "persist.hip", "pointwise.hip"]
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+SANITIZED_LIB = os.path.join(BUILD, "libwsfft_hostsan.so")
+
+
+def asan_runtime() -> str:
+    pat = os.path.join(os.path.dirname(os.path.dirname(HIPCC)), "llvm", "lib", "clang", "*", "lib", "linux",
+                       "libclang_rt.asan-x86_64.so")
+    found = sorted(glob.glob(pat))
+    return found[-1] if found else ""
+
+
+def build_host_sanitized() -> str:
+    """Builds SANITIZED_LIB from the kernel objects of a previous build; returns
+    its path, or "" when those objects are missing."""
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    objs = []
+    for src in srcs:
+        name = os.path.basename(src)
+        if name in SANITIZED_UNITS:
+            obj = os.path.join(BUILD, name + ".hostsan.o")
+            cmd = [HIPCC, *CXXFLAGS, *EXTRA_FLAGS.get(name, []), *HOST_SANITIZE, "-g", "-c", src, "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+            objs.append(obj)
+        else:
+            obj = os.path.join(BUILD, name + ".o")
+            if not os.path.exists(obj):
+                return ""
+            objs.append(obj)
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *HOST_SANITIZE, "-shared-libsan",
+           "-o", SANITIZED_LIB + ".tmp", *objs]
+    subprocess.check_call(cmd)
+    os.replace(SANITIZED_LIB + ".tmp", SANITIZED_LIB)
+    return SANITIZED_LIB
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--incremental", action="store_true")
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--host-sanitized", action="store_true",
+                    help="also build the host-sanitized library for the CPU tests")
     a = ap.parse_args()
     print(build(a.incremental, a.jobs))
+    if a.host_sanitized:
+        print(build_host_sanitized())
 
 
 if __name__ == "__main__":

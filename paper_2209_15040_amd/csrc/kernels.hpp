@@ -23,13 +23,16 @@ struct PassKernel {
     int fused;          // 0: plain pass; complex64 only: Poisson solve passes
                         // 1 real input, 2 times -1/|k|^2, 3 real output;
                         // 4 R2C x pass, 5 C2R x pass, 6 fused solve z pass,
-                        // 7 strided pass with cached loads and stores
+                        // 7 strided pass with cached loads and stores,
+                        // 8 fused x and y passes of whole planes
+    int n2;             // fused plane passes: the y length (n is the x length)
 };
 
 enum FusedKind {
     kFusedNone = 0, kFusedRealIn = 1, kFusedPoisson = 2, kFusedRealOut = 3,
     kFusedR2C = 4, kFusedC2R = 5, kFusedSolveZ = 6,
-    kFusedCached = 7   // a plain strided pass with cached (not streaming) loads and stores
+    kFusedCached = 7,  // a plain strided pass with cached (not streaming) loads and stores
+    kFusedPlane = 8    // the x and y transforms of whole xy-planes in LDS (plane.hip)
 };
 
 // NULL when no kernel of that length/layout/variant exists.
@@ -56,5 +59,7 @@ const PassKernel* find_fused_c64_pos(int n, bool strided, int fused);
 // the complex transform (half the real length for the x passes).
 const PassKernel* find_real_c64_neg(int n, bool strided, int fused);
 const PassKernel* find_real_c64_pos(int n, bool strided, int fused);
+// Fused x + y plane pass of complex64 nx x ny planes; NULL when none exists.
+const PassKernel* find_plane_kernel(int nx, int ny, int sign);
 
 }  // namespace wsfft

@@ -61,6 +61,8 @@ struct Pass {
     int outer_dim;                // count whose stride spans whole arrays: 0 = C, 1 = O1, 2 = O2
     int variant;                  // kernel launch variant (autotuner)
     dim3 grid;
+    bool plane = false;           // fused x + y pass over whole planes (n = nx, n2 = ny;
+    int64_t n2 = 0;               // tw_off / tw4_off: the x / y stage tables)
 };
 
 bool is_smooth23(int64_t n) {
@@ -255,6 +257,12 @@ void describe_passes(std::string& out, const std::vector<Pass>& passes) {
     for (const Pass& P : passes) {
         const int fu = P.kern_neg->fused;
         const char* what = fu == kFusedR2C ? "r2c" : (fu == kFusedC2R ? "c2r" : (fu == kFusedCached ? "cached-" : ""));
+        if (P.plane) {
+            std::snprintf(buf, sizeof buf, " xy[plane %lldx%lld wg=%d lds=%d grid=%u]", (long long)P.n, (long long)P.n2,
+                          P.kern_neg->threads, P.kern_neg->lds_bytes, P.grid.x);
+            out += buf;
+            continue;
+        }
         std::snprintf(buf, sizeof buf, " %c%s[%s%s n=%lld v%d wg=%d per=%d lds=%d grid=%u%s]", "xyz"[P.axis],
                       P.four_step == 1 ? "A" : (P.four_step == 2 ? "B" : ""), what, P.strided ? "strided" : "contig",
                       (long long)P.n, P.variant, P.kern_neg->threads, P.kern_neg->per_block, P.kern_neg->lds_bytes,
@@ -459,7 +467,7 @@ void tune_plan(wsfft_plan_s* plan, bool requested) {
         const int v = std::atoi(force);
         for (Pass& P : plan->passes) {
             Pass Q = P;
-            if (v >= 0 && v < kMaxVariants && use_variant(plan, Q, v)) P = Q;
+            if (!P.plane && v >= 0 && v < kMaxVariants && use_variant(plan, Q, v)) P = Q;
         }
         (void)hipGetLastError();
         return;
@@ -482,6 +490,7 @@ void tune_plan(wsfft_plan_s* plan, bool requested) {
     hipStream_t st = nullptr;
     const int64_t bytes = plan->n[0] * plan->n[1] * plan->n[2] * elem_bytes(plan->dtype);
     for (Pass& P : plan->passes) {
+        if (P.plane) continue;   // one kernel per plane shape
         const StorageKind kind = kind_of(plan->dtype, plan->flags);
         int nvar = 0;
         for (int v = 0; v < kMaxVariants; ++v)
@@ -530,9 +539,22 @@ void tune_plan(wsfft_plan_s* plan, bool requested) {
 
 }  // namespace
 
+namespace {
+// A C caller may pass any int for an enum parameter; its bits are read as an
+// int (loading an out-of-range value as the C++ enum type would be undefined).
+template <class E> int enum_bits(const E& e) {
+    static_assert(sizeof(E) == sizeof(int), "C enums are int-sized");
+    int v;
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
+
+}  // namespace
+
 extern "C" {
 
-const char* wsfft_status_string(wsfft_status_t st) {
+const char* wsfft_status_string(wsfft_status_t st_in) {
+    const int st = enum_bits(st_in);
     switch (st) {
         case WSFFT_SUCCESS: return "success";
         case WSFFT_ERROR_INVALID_VALUE: return "invalid value";
@@ -551,14 +573,16 @@ const char* wsfft_status_string(wsfft_status_t st) {
 
 wsfft_status_t wsfft_get_last_error(void) { return g_last_error; }
 
-wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtype_t dtype, int sign,
-                                  unsigned flags) {
+}  // extern "C"
+
+static wsfft_plan_t plan_create(int64_t nx, int64_t ny, int64_t nz, int dt, int sign, unsigned flags) {
     // ---- argument checks, no device calls -------------------------------
     if (nx < 1 || ny < 1 || nz < 1) return fail(WSFFT_ERROR_INVALID_VALUE);
     if (sign != 1 && sign != -1) return fail(WSFFT_ERROR_INVALID_VALUE);
-    if (dtype != WSFFT_C64 && dtype != WSFFT_C16_FP16 && dtype != WSFFT_C16_BF16)
+    if (dt != WSFFT_C64 && dt != WSFFT_C16_FP16 && dt != WSFFT_C16_BF16) return fail(WSFFT_ERROR_INVALID_VALUE);
+    const wsfft_dtype_t dtype = static_cast<wsfft_dtype_t>(dt);
+    if (flags & ~(WSFFT_FLAG_FP32_TWIDDLES | WSFFT_FLAG_TUNE | WSFFT_FLAG_FP16_MATH | WSFFT_FLAG_NO_PLANE))
         return fail(WSFFT_ERROR_INVALID_VALUE);
-    if (flags & ~(WSFFT_FLAG_FP32_TWIDDLES | WSFFT_FLAG_TUNE | WSFFT_FLAG_FP16_MATH)) return fail(WSFFT_ERROR_INVALID_VALUE);
     if ((flags & WSFFT_FLAG_FP16_MATH) && dtype != WSFFT_C16_FP16) return fail(WSFFT_ERROR_INVALID_VALUE);
     const int64_t dims[3] = {nx, ny, nz};
     for (int64_t d : dims)
@@ -590,10 +614,32 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
 
     const StorageKind kind = kind_of(dtype, flags);
     int S = 0;
+    // complex64 arrays whose x and y axes are both one pass and whose
+    // xy-plane fits in LDS fuse the two into one plane pass (plane.hip)
+    const bool plane = kind == kC64 && !(flags & WSFFT_FLAG_NO_PLANE) && nx > 1 && ny > 1 &&
+                       direct_ok(nx, false) && direct_ok(ny, true) && find_plane_kernel((int)nx, (int)ny, -1) &&
+                       find_plane_kernel((int)nx, (int)ny, +1);
     for (const AxisGeo& g : order) {
         const bool is_split = !direct_ok(g.n, g.inner != 1);
         const int sp = half ? (int)std::ceil(std::log2((double)g.n) / 2.0) : 0;
         S += sp;
+        if (plane && g.axis == 1) continue;   // done by the plane pass
+        if (plane && g.axis == 0) {
+            Pass P{};
+            set_direct(P, g);
+            PassArgs& a = P.args;
+            a.C = nz;                         // planes of nx * ny values
+            a.es_in = a.es_out = 1;
+            a.os1_in = a.os1_out = nx * ny;
+            P.axis = 0; P.n = nx; P.n2 = ny; P.plane = true; P.four_step = 0;
+            P.strided = false;
+            P.outer_dim = 0;
+            P.tw_off = table_for(kStage, nx);
+            P.tw4_off = table_for(kStage, ny);
+            P.pass_scale = 1.0f;
+            plan->passes.push_back(P);
+            continue;
+        }
         if (!is_split) {
             Pass P{};
             set_direct(P, g);
@@ -638,8 +684,13 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
 
     // kernels
     for (Pass& P : plan->passes) {
-        P.kern_neg = find_pass_kernel(kind, -1, (int)P.n, P.strided, P.four_step == 1);
-        P.kern_pos = find_pass_kernel(kind, +1, (int)P.n, P.strided, P.four_step == 1);
+        if (P.plane) {
+            P.kern_neg = find_plane_kernel((int)P.n, (int)P.n2, -1);
+            P.kern_pos = find_plane_kernel((int)P.n, (int)P.n2, +1);
+        } else {
+            P.kern_neg = find_pass_kernel(kind, -1, (int)P.n, P.strided, P.four_step == 1);
+            P.kern_pos = find_pass_kernel(kind, +1, (int)P.n, P.strided, P.four_step == 1);
+        }
         if (!P.kern_neg || !P.kern_pos) { delete plan; return fail(WSFFT_ERROR_UNSUPPORTED_SIZE); }
         // one grid dimension holds at most 2^32 - 1 work-items
         const int64_t blocks = blocks_for(P, P.kern_neg);
@@ -701,6 +752,8 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     for (Pass& P : plan->passes) {
         set_stage_tw(plan, P);
         P.args.tw4 = P.tw4_off >= 0 ? plan->tw_dev + P.tw4_off : nullptr;
+        // the plane pass's y stage table: the block of its kernel's radix plan
+        if (P.plane) P.args.tw4 += (int64_t)P.kern_neg->plan * P.n2;
         if (P.kern_neg->prepare() != hipSuccess || P.kern_pos->prepare() != hipSuccess) {
             (void)hipFree(plan->tw_dev);
             if (plan->work) (void)hipFree(plan->work);
@@ -719,8 +772,15 @@ wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtyp
     return plan;
 }
 
+extern "C" {
+
+wsfft_plan_t wsfft_plan_create_ex(int64_t nx, int64_t ny, int64_t nz, wsfft_dtype_t dtype, int sign,
+                                  unsigned flags) {
+    return plan_create(nx, ny, nz, enum_bits(dtype), sign, flags);
+}
+
 wsfft_plan_t wsfft_plan_create(int64_t nx, int64_t ny, int64_t nz, wsfft_dtype_t dtype, int sign) {
-    return wsfft_plan_create_ex(nx, ny, nz, dtype, sign, 0u);
+    return plan_create(nx, ny, nz, enum_bits(dtype), sign, 0u);
 }
 
 // Real plans.  The forward transform of a real nx x ny x nz array keeps the
@@ -1004,10 +1064,18 @@ bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out,
 // arrays (one BatchTable each); split-axis passes launch one by one.
 bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const* in, void* const* out,
                          int mode, size_t pi, hipStream_t stream) {
+    // Entries whose passes differ only in the launch variant the tuner chose
+    // for them alone share one launch: the group runs the variant most of its
+    // entries chose (ties: the lowest), so tuned plans never split a launch
+    // that untuned ones would share.
     struct Group {
-        const PassKernel* k;
+        const PassKernel* k0;          // any member's kernel (its shape and kind)
+        StorageKind kind;
+        int sign;
         unsigned twbits;
+        int votes[kMaxVariants];
         std::vector<int> idx;
+        const PassKernel* k;           // the kernel the group runs
     };
     std::vector<Group> groups;
     for (int i = 0; i < count; ++i) {
@@ -1020,15 +1088,27 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
         }
         const int sign = mode == 0 ? p->sign : -p->sign;
         const PassKernel* k = sign < 0 ? P.kern_neg : P.kern_pos;
+        const StorageKind kind = kind_of(p->dtype, p->flags);
         const unsigned twbits = (unsigned)p->dtype * 2u + (p->flags & WSFFT_FLAG_FP32_TWIDDLES ? 1u : 0u);
         Group* g = nullptr;
         for (Group& q : groups)
-            if (q.k == k && q.twbits == twbits) g = &q;
+            if (q.k0->n == k->n && q.k0->n2 == k->n2 && q.k0->strided == k->strided && q.k0->fused == k->fused &&
+                q.kind == kind && q.sign == sign && q.twbits == twbits)
+                g = &q;
         if (!g) {
-            groups.push_back({k, twbits, {}});
+            groups.push_back({k, kind, sign, twbits, {}, {}, k});
             g = &groups.back();
         }
+        if (k->variant >= 0 && k->variant < kMaxVariants) ++g->votes[k->variant];
         g->idx.push_back(i);
+    }
+    for (Group& g : groups) {
+        if (g.k0->fused != 0) continue;   // fused kernels have no variants
+        int best = 0;
+        for (int v = 1; v < kMaxVariants; ++v)
+            if (g.votes[v] > g.votes[best]) best = v;
+        const PassKernel* k = find_pass_kernel(g.kind, g.sign, g.k0->n, g.k0->strided, false, best);
+        if (k && k->prepare() == hipSuccess) g.k = k;
     }
     for (const Group& g : groups) {
         for (size_t c0 = 0; c0 < g.idx.size(); c0 += kMaxBatchDescs) {
@@ -1060,7 +1140,11 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
                 d.scale = mode == 2 ? P.inv_scale : P.pass_scale;
                 tiles += blocks_for(P, g.k);
                 d.tile_end = tiles;
-                if (e == c0) shared = P.args;
+                if (e == c0) {
+                    shared = P.args;
+                    // the stage twiddles of the group kernel's radix plan
+                    if (!P.plane) shared.tw = p->tw_dev + P.tw_off + (int64_t)g.k->plan * P.n;
+                }
             }
             if (tiles * g.k->threads > 0xffffffffLL) return false;
             if (g.k->launch(shared, &bt, dim3((unsigned)tiles), stream) != hipSuccess) return false;
@@ -1361,6 +1445,9 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
     if (!plans || !in || !out) return batch_fail(WSFFT_ERROR_NULL_POINTER);
     int sign = 0;
     size_t maxp = 0;
+    // each plan's passes for the persistent kernel: a fused plane pass runs as
+    // its x and y passes there (the kernel has no plane branch)
+    std::vector<std::vector<Pass>> lists((size_t)count);
     for (int i = 0; i < count; ++i) {
         const wsfft_status_t st = check_exec(plans[i], in[i], out[i]);
         if (st != WSFFT_SUCCESS) return batch_fail(st);
@@ -1369,10 +1456,31 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
         const int s = adjoint ? -p->sign : p->sign;
         if (sign == 0) sign = s;
         if (s != sign) return batch_fail(WSFFT_ERROR_INVALID_VALUE);
-        for (const Pass& P : p->passes)
+        for (const Pass& P : p->passes) {
+            if (!P.plane) {
+                lists[i].push_back(P);
+                continue;
+            }
+            const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+            Pass X{}, Y{};
+            set_direct(X, AxisGeo{0, nx, 1, ny * nz});
+            set_direct(Y, AxisGeo{1, ny, nx, nz});
+            X.axis = 0; X.n = nx; X.tw_off = P.tw_off;
+            Y.axis = 1; Y.n = ny; Y.tw_off = P.tw4_off;
+            for (Pass* Q : {&X, &Y}) {
+                Q->four_step = 0;
+                Q->pass_scale = Q->inv_scale = 1.0f;
+                Q->src_sel = Q->src_sel_ip = 1;
+                Q->dst_sel = Q->dst_sel_ip = 1;
+            }
+            X.src_sel = P.src_sel; X.src_sel_ip = P.src_sel_ip;   // the plane pass's input
+            lists[i].push_back(X);
+            lists[i].push_back(Y);
+        }
+        for (const Pass& P : lists[i])
             if (P.four_step != 0 || persist_type((int)P.n, P.strided) < 0)
                 return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
-        maxp = std::max(maxp, p->passes.size());
+        maxp = std::max(maxp, lists[i].size());
     }
     if (maxp > (size_t)kPersistMaxLevels) return batch_fail(WSFFT_ERROR_UNSUPPORTED_SIZE);
     // superstep-major list of passes
@@ -1382,8 +1490,8 @@ wsfft_batch_plan_t wsfft_batch_plan_create(int count, const wsfft_plan_t* plans,
     for (size_t pi = 0; pi < maxp; ++pi) {
         for (int i = 0; i < count; ++i) {
             const wsfft_plan_s* p = plans[i];
-            if (pi >= p->passes.size()) continue;
-            const Pass& P = p->passes[pi];
+            if (pi >= lists[i].size()) continue;
+            const Pass& P = lists[i][pi];
             PersistPass q{};
             q.a = P.args;
             // the stage twiddles of the persistent branch's radix plan

@@ -208,9 +208,12 @@ def test_poisson_fused_gradient_and_in_place(ws):
     # complex64) and with a real plan (work: the half spectrum)
     want = oracle.poisson_apply(f.astype(np.float32).astype(np.float64))
     x = torch.from_numpy(f.astype(np.float32)).cuda()
-    plan = ws.get_plan(torch.empty(x.shape, dtype=torch.complex64, device="cuda"), -1)
+    plan = ws.Plan(n, n, n, "c64", -1, ws.FLAG_NO_PLANE)
     work = torch.empty(x.shape, dtype=torch.complex64, device="cuda")
     assert ws._poisson_solve(plan.handle, x.data_ptr(), x.data_ptr(), work.data_ptr(), ws._stream(None)) == 0
+    # a complex plan with a fused plane pass has no six-pass solve
+    assert ws._poisson_solve(ws.Plan(n, n, n, "c64", -1).handle, x.data_ptr(), x.data_ptr(), work.data_ptr(),
+                             ws._stream(None)) == 2
     assert rel_l2(to_host(x), want) <= 1e-6
     x = torch.from_numpy(f.astype(np.float32)).cuda()
     rp = ws.RealPlan(n, n, n)

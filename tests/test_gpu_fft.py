@@ -234,3 +234,40 @@ def test_longest_axes(ws, shape):
     assert e <= TOL
     y2, _ = run_plan(ws, a, -1, "execute_inverse")
     assert rel_l2(y2, oracle.fftn(a.astype(np.complex128), +1) / a.size) <= TOL
+
+
+# --- fused x + y plane passes -------------------------------------------------------
+
+PLANE_PAIRS = [(32, 32), (32, 64), (64, 32), (32, 96), (96, 32), (32, 128), (128, 32), (32, 256), (256, 32),
+               (64, 64), (64, 96), (96, 64), (64, 128), (128, 64)]
+
+
+@pytest.mark.parametrize("nx,ny", PLANE_PAIRS, ids=lambda v: str(v))
+def test_plane_pass_shapes(ws, nx, ny):
+    """Every (nx, ny) with a fused plane pass, with a few planes (nz = 3) and
+    as a 2D array: forward, adjoint and inverse against the oracle, and the
+    same bits as the separate x and y passes would give up to rounding."""
+    for nz in (3, 1):
+        a = synth.normal_c((nz, ny, nx), seed=nx * 7 + ny + nz).astype(np.complex64)
+        p = ws.Plan(nx, ny, nz, "c64", -1)
+        assert "plane" in p.describe(), p.describe()
+        assert p.num_passes == (2 if nz > 1 else 1)
+        x = to_dev(a)
+        a64 = a.astype(np.complex128)
+        assert rel_l2(to_host(p.execute(x)), oracle.fftn(a64, -1)) <= TOL
+        assert rel_l2(to_host(p.execute_adjoint(x)), oracle.fftn(a64, +1)) <= TOL
+        assert rel_l2(to_host(p.execute_inverse(x)), oracle.fftn(a64, +1) / a.size) <= TOL
+        q = ws.Plan(nx, ny, nz, "c64", -1, ws.FLAG_NO_PLANE)
+        assert "plane" not in q.describe()
+        assert rel_l2(to_host(p.execute(x)), to_host(q.execute(x))) <= TOL
+
+
+def test_plane_pass_in_place_and_32cubed(ws):
+    """32^3 (the plain forward workload) runs as a plane pass and a z pass;
+    in place as well."""
+    a = synth.uniform_c((32, 32, 32), seed=0).astype(np.complex64)
+    p = ws.Plan(32, 32, 32, "c64", -1)
+    assert p.num_passes == 2, p.describe()
+    x = to_dev(a)
+    p.execute(x, out=x)
+    assert rel_l2(to_host(x), oracle.fftn(a.astype(np.complex128), -1)) <= TOL

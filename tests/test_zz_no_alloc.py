@@ -42,7 +42,7 @@ def test_noalloc_matches_solve_two_calls(ws, kind):
             plan = ws.RealPlan(nx, ny, nz)
             wshape = (nz, ny, nx // 2 + 1)
         else:
-            plan = ws.Plan(nx, ny, nz, "c64", -1)
+            plan = ws.Plan(nx, ny, nz, "c64", -1, ws.FLAG_NO_PLANE)   # the six-pass complex solve
             wshape = (nz, ny, nx)
         assert 8 * int(np.prod(wshape)) <= SCRATCH_BYTES
         _solve_both(ws, plan, (nz, ny, nx), wshape, seed=60 + i)
