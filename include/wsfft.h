@@ -105,6 +105,17 @@ typedef enum {
  * supersteps into one pass over whole planes in LDS (two HBM round trips
  * for a 3D array instead of three).  This flag keeps them separate. */
 #define WSFFT_FLAG_NO_PLANE 8u
+/* Infinity Cache policy.  WSFFT_C64 3D plans of three single passes (x, y, z)
+ * by default route data through the 256 MB Infinity Cache by array size A:
+ * 64 MiB < A <= 128 MiB: every pass with cached loads and stores (the next
+ * pass reads its input from the cache); 128 MiB < A <= 256 MiB: the x pass
+ * with cached stores; A > 256 MiB: the x and y passes run chunk by chunk
+ * over groups of xy-planes of at most 256 MiB, the x pass of a chunk with
+ * cached stores, so that its y pass reads the chunk from the cache (the z
+ * pass then runs once over the whole array).  Results are bitwise equal to
+ * the streaming schedule; only the memory traffic differs.  This flag keeps
+ * every pass streaming (non-temporal loads and stores, no chunks). */
+#define WSFFT_FLAG_STREAMING 16u
 
 /*
  * Autotuning.  Passes of the hot lengths (powers of two up to 1024 strided,
@@ -176,8 +187,9 @@ wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const
 /* Enqueue only pass `index` (0-based, < wsfft_plan_num_passes) of the
  * transform wsfft_execute (mode 0), wsfft_execute_adjoint (1) or
  * wsfft_execute_inverse (2) would run, with the same buffers.  Running every
- * index in order equals the full call; one index alone is for per-pass timing
- * and profiling.  On a real plan, mode 0 indexes the passes of
+ * index in order equals the full call (a plan whose x and y passes run in
+ * plane chunks runs each over the whole array here); one index alone is for
+ * per-pass timing and profiling.  On a real plan, mode 0 indexes the passes of
  * wsfft_execute_r2c, modes 1 and 2 those of wsfft_execute_c2r and
  * wsfft_execute_c2r_inverse (4-byte alignment is checked for both buffers). */
 wsfft_status_t wsfft_execute_pass(wsfft_plan_t plan, int index, int mode, const void* in, void* out,

@@ -31,6 +31,7 @@ FLAG_FP32_TWIDDLES = 1
 FLAG_TUNE = 2
 FLAG_FP16_MATH = 4       # FP16 plans: packed FP16 butterfly arithmetic
 FLAG_NO_PLANE = 8        # complex64 plans: keep the x and y passes separate (no fused plane pass)
+FLAG_STREAMING = 16      # complex64 plans: every pass streaming, no Infinity Cache policy (no plane chunks)
 DTYPES = {"c64": C64, "fp16": C16_FP16, "bf16": C16_BF16}
 _TORCH_DTYPE = {C64: torch.complex64, C16_FP16: torch.float16, C16_BF16: torch.bfloat16}
 
@@ -126,8 +127,9 @@ class Plan:
     """A wsfft plan for an nx x ny x nz transform (``wsfft_plan_create_ex``).
 
     ``dtype``: "c64", "fp16" or "bf16" (16-bit tensors carry a trailing
-    (re, im) axis).  ``flags``: FLAG_FP32_TWIDDLES, FLAG_TUNE and, for "fp16",
-    FLAG_FP16_MATH (packed FP16 butterflies instead of FP32 arithmetic)."""
+    (re, im) axis).  ``flags``: FLAG_FP32_TWIDDLES, FLAG_TUNE, for "fp16"
+    FLAG_FP16_MATH (packed FP16 butterflies instead of FP32 arithmetic), and
+    for "c64" FLAG_NO_PLANE and FLAG_STREAMING."""
 
     def __init__(self, nx: int, ny: int = 1, nz: int = 1, dtype="c64", sign: int = -1, flags: int = 0):
         self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)

@@ -23,16 +23,18 @@ struct PassKernel {
     int fused;          // 0: plain pass; complex64 only: Poisson solve passes
                         // 1 real input, 2 times -1/|k|^2, 3 real output;
                         // 4 R2C x pass, 5 C2R x pass, 6 fused solve z pass,
-                        // 7 strided pass with cached loads and stores,
-                        // 8 fused x and y passes of whole planes
+                        // 7 pass with cached loads and stores,
+                        // 8 fused x and y passes of whole planes,
+                        // 9 contiguous pass with streaming loads and cached stores
     int n2;             // fused plane passes: the y length (n is the x length)
 };
 
 enum FusedKind {
     kFusedNone = 0, kFusedRealIn = 1, kFusedPoisson = 2, kFusedRealOut = 3,
     kFusedR2C = 4, kFusedC2R = 5, kFusedSolveZ = 6,
-    kFusedCached = 7,  // a plain strided pass with cached (not streaming) loads and stores
-    kFusedPlane = 8    // the x and y transforms of whole xy-planes in LDS (plane.hip)
+    kFusedCached = 7,  // a plain pass with cached (not streaming) loads and stores
+    kFusedPlane = 8,   // the x and y transforms of whole xy-planes in LDS (plane.hip)
+    kFusedCachedStore = 9   // a plain contiguous pass with streaming loads and cached stores
 };
 
 // NULL when no kernel of that length/layout/variant exists.
@@ -59,6 +61,11 @@ const PassKernel* find_fused_c64_pos(int n, bool strided, int fused);
 // the complex transform (half the real length for the x passes).
 const PassKernel* find_real_c64_neg(int n, bool strided, int fused);
 const PassKernel* find_real_c64_pos(int n, bool strided, int fused);
+// Complex64 passes that go through the caches (kind kFusedCached: cached
+// loads and stores, both layouts; kFusedCachedStore: contiguous, streaming
+// loads and cached stores).  NULL when none exists.
+const PassKernel* find_cached_c64_neg(int n, bool strided, int fused);
+const PassKernel* find_cached_c64_pos(int n, bool strided, int fused);
 // Fused x + y plane pass of complex64 nx x ny planes; NULL when none exists.
 const PassKernel* find_plane_kernel(int nx, int ny, int sign);
 

@@ -156,6 +156,11 @@ struct wsfft_plan_s {
     float2* tw_dev = nullptr;     // all twiddle tables, one block
     void* work = nullptr;         // four-step work buffer (or null)
     int64_t work_bytes = 0;
+    // Infinity Cache policy of complex64 x, y, z plans (WSFFT_FLAG_STREAMING):
+    // 0 streaming, 1 cached loads and stores, 2 cached x stores, 3 x and y in
+    // plane chunks of chunk_planes planes with cached x stores
+    int cache_mode = 0;
+    int64_t chunk_planes = 0;
     std::string desc;
 };
 
@@ -256,7 +261,11 @@ void describe_passes(std::string& out, const std::vector<Pass>& passes) {
     char buf[256];
     for (const Pass& P : passes) {
         const int fu = P.kern_neg->fused;
-        const char* what = fu == kFusedR2C ? "r2c" : (fu == kFusedC2R ? "c2r" : (fu == kFusedCached ? "cached-" : ""));
+        const char* what = fu == kFusedR2C      ? "r2c"
+                           : fu == kFusedC2R    ? "c2r"
+                           : fu == kFusedCached ? "cached-"
+                           : fu == kFusedCachedStore ? "cached-store-"
+                                                : "";
         if (P.plane) {
             std::snprintf(buf, sizeof buf, " xy[plane %lldx%lld wg=%d lds=%d grid=%u]", (long long)P.n, (long long)P.n2,
                           P.kern_neg->threads, P.kern_neg->lds_bytes, P.grid.x);
@@ -278,6 +287,10 @@ void describe_plan(wsfft_plan_s* plan) {
                   plan->scale_log2);
     plan->desc = buf;
     describe_passes(plan->desc, plan->passes);
+    if (plan->chunk_planes > 0) {
+        std::snprintf(buf, sizeof buf, " (x, y in chunks of %lld planes)", (long long)plan->chunk_planes);
+        plan->desc += buf;
+    }
     if (plan->real) {
         plan->desc += " | c2r:";
         describe_passes(plan->desc, plan->cpasses);
@@ -467,7 +480,7 @@ void tune_plan(wsfft_plan_s* plan, bool requested) {
         const int v = std::atoi(force);
         for (Pass& P : plan->passes) {
             Pass Q = P;
-            if (!P.plane && v >= 0 && v < kMaxVariants && use_variant(plan, Q, v)) P = Q;
+            if (!P.plane && P.kern_neg->fused == 0 && v >= 0 && v < kMaxVariants && use_variant(plan, Q, v)) P = Q;
         }
         (void)hipGetLastError();
         return;
@@ -490,7 +503,9 @@ void tune_plan(wsfft_plan_s* plan, bool requested) {
     hipStream_t st = nullptr;
     const int64_t bytes = plan->n[0] * plan->n[1] * plan->n[2] * elem_bytes(plan->dtype);
     for (Pass& P : plan->passes) {
-        if (P.plane) continue;   // one kernel per plane shape
+        // one kernel per plane shape; passes of the Infinity Cache policy keep
+        // their cached kernels
+        if (P.plane || P.kern_neg->fused != 0) continue;
         const StorageKind kind = kind_of(plan->dtype, plan->flags);
         int nvar = 0;
         for (int v = 0; v < kMaxVariants; ++v)
@@ -575,13 +590,73 @@ wsfft_status_t wsfft_get_last_error(void) { return g_last_error; }
 
 }  // extern "C"
 
+namespace {
+// Infinity Cache policy of a complex64 plan of three single passes x, y, z
+// (see WSFFT_FLAG_STREAMING).  Measured on MI355X, by array size A:
+//  * A <= 64 MiB: streaming throughout (16 MiB ties; at 32-64 MiB cached
+//    passes win on 256 x 256 planes and lose on 512 x 512 ones);
+//  * 64 MiB < A <= 128 MiB: every pass with cached loads and stores, so each
+//    pass reads what the previous one left in the 256 MB Infinity Cache
+//    (256^3: 136.6 us per transform against 154.8 streaming);
+//  * 128 MiB < A <= 256 MiB: cached x stores only (512 x 512 x 128, x and y
+//    passes: 176 against 194.5 us; caching every pass there: 212 us);
+//  * A > 256 MiB: the x and y passes chunk by chunk over groups of planes of
+//    at most 256 MiB, the x pass of a chunk with cached stores so that its y
+//    pass reads the chunk from the cache (512^3: 4 chunks, 1107 against
+//    1146 us; 1024^3: 32 chunks, 10.37 against 11.13 ms); chunks of a larger
+//    share of the cache, or streaming x stores, lose it again.
+// The cached kernels have the launch geometry of the default ones, so the
+// results are bitwise equal and the grids unchanged.
+bool use_cached(Pass& P, int fused) {
+    const PassKernel* kn = find_cached_c64_neg((int)P.n, P.strided, fused);
+    const PassKernel* kp = find_cached_c64_pos((int)P.n, P.strided, fused);
+    if (!kn || !kp || kn->per_block != P.kern_neg->per_block || kn->threads != P.kern_neg->threads) return false;
+    P.kern_neg = kn;
+    P.kern_pos = kp;
+    return true;
+}
+
+void apply_cache_policy(wsfft_plan_s* plan) {
+    auto& ps = plan->passes;
+    const int64_t nx = plan->n[0], ny = plan->n[1], nz = plan->n[2];
+    if (ps.size() != 3 || nz < 2) return;
+    for (int i = 0; i < 3; ++i)
+        if (ps[i].plane || ps[i].four_step != 0 || ps[i].axis != i || ps[i].strided != (i > 0)) return;
+    constexpr int64_t kMiB = int64_t(1) << 20, kCache = 256 * kMiB;
+    const int64_t plane = nx * ny * 8, A = plane * nz;
+    if (A <= 64 * kMiB) return;
+    if (A <= 128 * kMiB) {
+        Pass q[3] = {ps[0], ps[1], ps[2]};
+        for (Pass& P : q)
+            if (!use_cached(P, kFusedCached)) return;
+        for (int i = 0; i < 3; ++i) ps[i] = q[i];
+        plan->cache_mode = 1;
+        return;
+    }
+    if (A <= kCache) {
+        if (use_cached(ps[0], kFusedCachedStore)) plan->cache_mode = 2;
+        return;
+    }
+    // the largest group of planes dividing nz that fits the cache; at most
+    // 64 chunks
+    int64_t zc = 0;
+    for (int64_t z = nz - 1; z >= 1 && zc == 0; --z)
+        if (nz % z == 0 && z * plane <= kCache) zc = z;
+    if (zc == 0 || nz / zc > 64) return;
+    if (!use_cached(ps[0], kFusedCachedStore)) return;
+    plan->cache_mode = 3;
+    plan->chunk_planes = zc;
+}
+}  // namespace
+
 static wsfft_plan_t plan_create(int64_t nx, int64_t ny, int64_t nz, int dt, int sign, unsigned flags) {
     // ---- argument checks, no device calls -------------------------------
     if (nx < 1 || ny < 1 || nz < 1) return fail(WSFFT_ERROR_INVALID_VALUE);
     if (sign != 1 && sign != -1) return fail(WSFFT_ERROR_INVALID_VALUE);
     if (dt != WSFFT_C64 && dt != WSFFT_C16_FP16 && dt != WSFFT_C16_BF16) return fail(WSFFT_ERROR_INVALID_VALUE);
     const wsfft_dtype_t dtype = static_cast<wsfft_dtype_t>(dt);
-    if (flags & ~(WSFFT_FLAG_FP32_TWIDDLES | WSFFT_FLAG_TUNE | WSFFT_FLAG_FP16_MATH | WSFFT_FLAG_NO_PLANE))
+    if (flags & ~(WSFFT_FLAG_FP32_TWIDDLES | WSFFT_FLAG_TUNE | WSFFT_FLAG_FP16_MATH | WSFFT_FLAG_NO_PLANE |
+                  WSFFT_FLAG_STREAMING))
         return fail(WSFFT_ERROR_INVALID_VALUE);
     if ((flags & WSFFT_FLAG_FP16_MATH) && dtype != WSFFT_C16_FP16) return fail(WSFFT_ERROR_INVALID_VALUE);
     const int64_t dims[3] = {nx, ny, nz};
@@ -700,6 +775,7 @@ static wsfft_plan_t plan_create(int64_t nx, int64_t ny, int64_t nz, int dt, int 
         }
         P.grid = dim3((unsigned)blocks);
     }
+    if (kind == kC64 && !(flags & WSFFT_FLAG_STREAMING)) apply_cache_policy(plan);
 
     // buffers: split passes read the caller's input (first) or, for a
     // second split axis, the work buffer
@@ -871,8 +947,8 @@ wsfft_plan_t wsfft_plan_create_real(int64_t nx, int64_t ny, int64_t nz, unsigned
         for (Pass& P : ps) {
             P.pass_scale = P.inv_scale = 1.0f;
             if (misaligned && P.four_step == 0) {
-                P.kern_neg = find_real_c64_neg((int)P.n, true, kFusedCached);
-                P.kern_pos = find_real_c64_pos((int)P.n, true, kFusedCached);
+                P.kern_neg = find_cached_c64_neg((int)P.n, true, kFusedCached);
+                P.kern_pos = find_cached_c64_pos((int)P.n, true, kFusedCached);
                 P.args.xcd_order = 1;
             } else {
                 P.kern_neg = find_pass_kernel(kC64, -1, (int)P.n, true, P.four_step == 1);
@@ -1031,11 +1107,26 @@ wsfft_status_t check_real(const wsfft_plan_s* plan, const void* in, const void* 
 
 // Enqueue pass index `pi` of a plan; returns false on a launch error.  Real
 // plans: the R2C passes in mode 0, the C2R passes otherwise.
+// With zc > 0, only planes [z0, z0 + zc) of the x or y pass (a plane chunk).
 bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out, int mode,
-                 hipStream_t stream, int64_t batch = 1) {
+                 hipStream_t stream, int64_t batch = 1, int64_t z0 = 0, int64_t zc = 0) {
     const Pass& P = (plan->real && mode != 0) ? plan->cpasses[pi] : plan->passes[pi];
     PassArgs a = P.args;
     dim3 grid = P.grid;
+    int64_t chunk_off = 0;   // bytes
+    if (zc > 0) {
+        const int64_t per = P.kern_neg->per_block;
+        int64_t blocks;
+        if (P.axis == 0) {   // contiguous x pencils: ny per plane
+            a.C = plan->n[1] * zc;
+            blocks = (a.C + per - 1) / per;
+        } else {             // strided y pass: planes are the outer index
+            a.O1 = zc;
+            blocks = ((a.C + per - 1) / per) * a.O1 * a.O2;
+        }
+        grid = dim3((unsigned)blocks);
+        chunk_off = z0 * plan->n[0] * plan->n[1] * elem_bytes(plan->dtype);
+    }
     if (batch > 1) {   // `batch` arrays back to back: one more factor on the outermost count
         int64_t blocks;
         const int64_t per = P.kern_neg->per_block;
@@ -1051,8 +1142,8 @@ bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out,
         return s == 0 ? const_cast<void*>(in) : (s == 1 ? out : plan->work);
     };
     const bool ip = in == out;
-    a.src = sel(ip ? P.src_sel_ip : P.src_sel);
-    a.dst = sel(ip ? P.dst_sel_ip : P.dst_sel);
+    a.src = static_cast<const char*>(sel(ip ? P.src_sel_ip : P.src_sel)) + chunk_off;
+    a.dst = static_cast<char*>(sel(ip ? P.dst_sel_ip : P.dst_sel)) + chunk_off;
     a.scale = mode == 2 ? P.inv_scale : P.pass_scale;
     const int sign = mode == 0 ? plan->sign : -plan->sign;
     const PassKernel* k = sign < 0 ? P.kern_neg : P.kern_pos;
@@ -1160,7 +1251,15 @@ wsfft_status_t exec_plan(const wsfft_plan_s* plan, const void* in, void* out, in
             return WSFFT_ERROR_HIP;
         return WSFFT_SUCCESS;
     }
-    for (size_t i = 0; i < plan->passes.size(); ++i)
+    size_t first = 0;
+    if (plan->chunk_planes > 0) {   // x and y chunk by chunk (Infinity Cache policy)
+        const int64_t nz = plan->n[2], zc = plan->chunk_planes;
+        for (int64_t z0 = 0; z0 < nz; z0 += zc)
+            for (size_t i = 0; i < 2; ++i)
+                if (!launch_pass(plan, i, in, out, mode, stream, 1, z0, zc)) return WSFFT_ERROR_HIP;
+        first = 2;
+    }
+    for (size_t i = first; i < plan->passes.size(); ++i)
         if (!launch_pass(plan, i, in, out, mode, stream)) return WSFFT_ERROR_HIP;
     return WSFFT_SUCCESS;
 }
