@@ -105,16 +105,17 @@ typedef enum {
  * supersteps into one pass over whole planes in LDS (two HBM round trips
  * for a 3D array instead of three).  This flag keeps them separate. */
 #define WSFFT_FLAG_NO_PLANE 8u
-/* Infinity Cache policy.  WSFFT_C64 3D plans of three single passes (x, y, z)
- * by default route data through the 256 MB Infinity Cache by array size A:
- * 64 MiB < A <= 128 MiB: every pass with cached loads and stores (the next
- * pass reads its input from the cache); 128 MiB < A <= 256 MiB: the x pass
- * with cached stores; A > 256 MiB: the x and y passes run chunk by chunk
- * over groups of xy-planes of at most 256 MiB, the x pass of a chunk with
- * cached stores, so that its y pass reads the chunk from the cache (the z
- * pass then runs once over the whole array).  Results are bitwise equal to
- * the streaming schedule; only the memory traffic differs.  This flag keeps
- * every pass streaming (non-temporal loads and stores, no chunks). */
+/* Infinity Cache policy.  3D plans of three single passes (x, y, z) by
+ * default route data through the 256 MB Infinity Cache by array size A:
+ * 64 MiB < A <= 128 MiB (WSFFT_C64 only): every pass with cached loads and
+ * stores (the next pass reads its input from the cache); 128 MiB < A <=
+ * 256 MiB: the x pass with cached stores; A > 256 MiB: the x and y passes run
+ * chunk by chunk over groups of xy-planes of at most 256 MiB, the x pass of a
+ * chunk with cached stores, so that its y pass reads the chunk from the cache
+ * (the z pass then runs once over the whole array).  Results are bitwise
+ * equal to the streaming schedule; only the memory traffic differs.  This
+ * flag keeps every pass streaming (non-temporal loads and stores, no
+ * chunks). */
 #define WSFFT_FLAG_STREAMING 16u
 
 /*

@@ -61,11 +61,21 @@ const PassKernel* find_fused_c64_pos(int n, bool strided, int fused);
 // the complex transform (half the real length for the x passes).
 const PassKernel* find_real_c64_neg(int n, bool strided, int fused);
 const PassKernel* find_real_c64_pos(int n, bool strided, int fused);
-// Complex64 passes that go through the caches (kind kFusedCached: cached
-// loads and stores, both layouts; kFusedCachedStore: contiguous, streaming
-// loads and cached stores).  NULL when none exists.
-const PassKernel* find_cached_c64_neg(int n, bool strided, int fused);
-const PassKernel* find_cached_c64_pos(int n, bool strided, int fused);
+// Passes that go through the caches (kind kFusedCached: cached loads and
+// stores, both layouts, complex64 only; kFusedCachedStore: contiguous,
+// streaming loads and cached stores, every storage type).  NULL when none
+// exists.
+const PassKernel* find_cached_kernel(StorageKind kind, int sign, int n, bool strided, int fused);
+#define WSFFT_DECLARE_CACHED(NAME) const PassKernel* NAME(int n, bool strided, int fused);
+WSFFT_DECLARE_CACHED(find_cached_c64_neg)
+WSFFT_DECLARE_CACHED(find_cached_c64_pos)
+WSFFT_DECLARE_CACHED(find_cached_f16_neg)
+WSFFT_DECLARE_CACHED(find_cached_f16_pos)
+WSFFT_DECLARE_CACHED(find_cached_bf16_neg)
+WSFFT_DECLARE_CACHED(find_cached_bf16_pos)
+WSFFT_DECLARE_CACHED(find_cached_f16m_neg)
+WSFFT_DECLARE_CACHED(find_cached_f16m_pos)
+#undef WSFFT_DECLARE_CACHED
 // Fused x + y plane pass of complex64 nx x ny planes; NULL when none exists.
 const PassKernel* find_plane_kernel(int nx, int ny, int sign);
 

@@ -63,6 +63,10 @@ struct Pass {
     dim3 grid;
     bool plane = false;           // fused x + y pass over whole planes (n = nx, n2 = ny;
     int64_t n2 = 0;               // tw_off / tw4_off: the x / y stage tables)
+    // plane chunks (Infinity Cache policy): C per xy-plane (0: O1 counts the
+    // planes) and the bytes per plane of the source and destination
+    int64_t chunk_c = 0;
+    int64_t plane_in = 0, plane_out = 0;
 };
 
 bool is_smooth23(int64_t n) {
@@ -156,11 +160,12 @@ struct wsfft_plan_s {
     float2* tw_dev = nullptr;     // all twiddle tables, one block
     void* work = nullptr;         // four-step work buffer (or null)
     int64_t work_bytes = 0;
-    // Infinity Cache policy of complex64 x, y, z plans (WSFFT_FLAG_STREAMING):
-    // 0 streaming, 1 cached loads and stores, 2 cached x stores, 3 x and y in
-    // plane chunks of chunk_planes planes with cached x stores
+    // Infinity Cache policy of x, y, z plans (WSFFT_FLAG_STREAMING):
+    // 0 streaming, 1 cached loads and stores, 2 cached x stores, 3 two passes
+    // in plane chunks of chunk_planes planes: passes[chunk_at] and the next
     int cache_mode = 0;
     int64_t chunk_planes = 0;
+    int chunk_at = -1;
     std::string desc;
 };
 
@@ -591,8 +596,8 @@ wsfft_status_t wsfft_get_last_error(void) { return g_last_error; }
 }  // extern "C"
 
 namespace {
-// Infinity Cache policy of a complex64 plan of three single passes x, y, z
-// (see WSFFT_FLAG_STREAMING).  Measured on MI355X, by array size A:
+// Infinity Cache policy of a plan of three single passes x, y, z (see
+// WSFFT_FLAG_STREAMING).  Measured on MI355X with complex64, by array size A:
 //  * A <= 64 MiB: streaming throughout (16 MiB ties; at 32-64 MiB cached
 //    passes win on 256 x 256 planes and lose on 512 x 512 ones);
 //  * 64 MiB < A <= 128 MiB: every pass with cached loads and stores, so each
@@ -605,11 +610,13 @@ namespace {
 //    pass reads the chunk from the cache (512^3: 4 chunks, 1107 against
 //    1146 us; 1024^3: 32 chunks, 10.37 against 11.13 ms); chunks of a larger
 //    share of the cache, or streaming x stores, lose it again.
-// The cached kernels have the launch geometry of the default ones, so the
-// results are bitwise equal and the grids unchanged.
-bool use_cached(Pass& P, int fused) {
-    const PassKernel* kn = find_cached_c64_neg((int)P.n, P.strided, fused);
-    const PassKernel* kp = find_cached_c64_pos((int)P.n, P.strided, fused);
+// The 16-bit storage types have cached-store x kernels only (no cached
+// loads), so they take the last two rules.  The cached kernels have the
+// launch geometry of the default ones, so the results are bitwise equal and
+// the grids unchanged.
+bool use_cached(Pass& P, StorageKind kind, int fused) {
+    const PassKernel* kn = find_cached_kernel(kind, -1, (int)P.n, P.strided, fused);
+    const PassKernel* kp = find_cached_kernel(kind, +1, (int)P.n, P.strided, fused);
     if (!kn || !kp || kn->per_block != P.kern_neg->per_block || kn->threads != P.kern_neg->threads) return false;
     P.kern_neg = kn;
     P.kern_pos = kp;
@@ -619,22 +626,23 @@ bool use_cached(Pass& P, int fused) {
 void apply_cache_policy(wsfft_plan_s* plan) {
     auto& ps = plan->passes;
     const int64_t nx = plan->n[0], ny = plan->n[1], nz = plan->n[2];
+    const StorageKind kind = kind_of(plan->dtype, plan->flags);
     if (ps.size() != 3 || nz < 2) return;
     for (int i = 0; i < 3; ++i)
         if (ps[i].plane || ps[i].four_step != 0 || ps[i].axis != i || ps[i].strided != (i > 0)) return;
     constexpr int64_t kMiB = int64_t(1) << 20, kCache = 256 * kMiB;
-    const int64_t plane = nx * ny * 8, A = plane * nz;
+    const int64_t plane = nx * ny * elem_bytes(plan->dtype), A = plane * nz;
     if (A <= 64 * kMiB) return;
     if (A <= 128 * kMiB) {
         Pass q[3] = {ps[0], ps[1], ps[2]};
         for (Pass& P : q)
-            if (!use_cached(P, kFusedCached)) return;
+            if (!use_cached(P, kind, kFusedCached)) return;
         for (int i = 0; i < 3; ++i) ps[i] = q[i];
         plan->cache_mode = 1;
         return;
     }
     if (A <= kCache) {
-        if (use_cached(ps[0], kFusedCachedStore)) plan->cache_mode = 2;
+        if (use_cached(ps[0], kind, kFusedCachedStore)) plan->cache_mode = 2;
         return;
     }
     // the largest group of planes dividing nz that fits the cache; at most
@@ -643,9 +651,13 @@ void apply_cache_policy(wsfft_plan_s* plan) {
     for (int64_t z = nz - 1; z >= 1 && zc == 0; --z)
         if (nz % z == 0 && z * plane <= kCache) zc = z;
     if (zc == 0 || nz / zc > 64) return;
-    if (!use_cached(ps[0], kFusedCachedStore)) return;
+    if (!use_cached(ps[0], kind, kFusedCachedStore)) return;
     plan->cache_mode = 3;
     plan->chunk_planes = zc;
+    plan->chunk_at = 0;
+    ps[0].chunk_c = ny;                    // x: ny pencils per plane
+    ps[1].chunk_c = 0;                     // y: planes are its outer index
+    for (int i = 0; i < 2; ++i) ps[i].plane_in = ps[i].plane_out = plane;
 }
 }  // namespace
 
@@ -775,7 +787,7 @@ static wsfft_plan_t plan_create(int64_t nx, int64_t ny, int64_t nz, int dt, int 
         }
         P.grid = dim3((unsigned)blocks);
     }
-    if (kind == kC64 && !(flags & WSFFT_FLAG_STREAMING)) apply_cache_policy(plan);
+    if (!(flags & WSFFT_FLAG_STREAMING)) apply_cache_policy(plan);
 
     // buffers: split passes read the caller's input (first) or, for a
     // second split axis, the work buffer
@@ -999,7 +1011,6 @@ wsfft_plan_t wsfft_plan_create_real(int64_t nx, int64_t ny, int64_t nz, unsigned
             P.grid = dim3((unsigned)blocks);
         }
     if (plan->nsplit > 0) plan->work_bytes = nxh * ny * nz * 8;
-
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { delete plan; return fail(WSFFT_ERROR_NO_DEVICE); }
     if (hipGetDevice(&plan->device) != hipSuccess) { delete plan; return fail(WSFFT_ERROR_HIP); }
@@ -1113,19 +1124,15 @@ bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out,
     const Pass& P = (plan->real && mode != 0) ? plan->cpasses[pi] : plan->passes[pi];
     PassArgs a = P.args;
     dim3 grid = P.grid;
-    int64_t chunk_off = 0;   // bytes
+    int64_t in_off = 0, out_off = 0;   // bytes
     if (zc > 0) {
         const int64_t per = P.kern_neg->per_block;
-        int64_t blocks;
-        if (P.axis == 0) {   // contiguous x pencils: ny per plane
-            a.C = plan->n[1] * zc;
-            blocks = (a.C + per - 1) / per;
-        } else {             // strided y pass: planes are the outer index
-            a.O1 = zc;
-            blocks = ((a.C + per - 1) / per) * a.O1 * a.O2;
-        }
+        if (P.chunk_c > 0) a.C = P.chunk_c * zc;   // C counts the planes' pencils or columns
+        else a.O1 = zc;                           // the outer index counts planes
+        const int64_t blocks = P.strided ? ((a.C + per - 1) / per) * a.O1 * a.O2 : (a.C + per - 1) / per;
         grid = dim3((unsigned)blocks);
-        chunk_off = z0 * plan->n[0] * plan->n[1] * elem_bytes(plan->dtype);
+        in_off = z0 * P.plane_in;
+        out_off = z0 * P.plane_out;
     }
     if (batch > 1) {   // `batch` arrays back to back: one more factor on the outermost count
         int64_t blocks;
@@ -1142,8 +1149,8 @@ bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out,
         return s == 0 ? const_cast<void*>(in) : (s == 1 ? out : plan->work);
     };
     const bool ip = in == out;
-    a.src = static_cast<const char*>(sel(ip ? P.src_sel_ip : P.src_sel)) + chunk_off;
-    a.dst = static_cast<char*>(sel(ip ? P.dst_sel_ip : P.dst_sel)) + chunk_off;
+    a.src = static_cast<const char*>(sel(ip ? P.src_sel_ip : P.src_sel)) + in_off;
+    a.dst = static_cast<char*>(sel(ip ? P.dst_sel_ip : P.dst_sel)) + out_off;
     a.scale = mode == 2 ? P.inv_scale : P.pass_scale;
     const int sign = mode == 0 ? plan->sign : -plan->sign;
     const PassKernel* k = sign < 0 ? P.kern_neg : P.kern_pos;
@@ -1244,6 +1251,25 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
     return true;
 }
 
+// Every pass of a list in order; passes `at` and `at + 1` (at >= 0) run
+// chunk by chunk over groups of chunk_planes xy-planes, the two passes of a
+// chunk back to back, so the second reads what the first left in the cache.
+wsfft_status_t run_passes(const wsfft_plan_s* plan, size_t count, int at, const void* in, void* out, int mode,
+                          hipStream_t stream) {
+    for (size_t i = 0; i < count; ++i) {
+        if (at >= 0 && plan->chunk_planes > 0 && i == (size_t)at) {
+            const int64_t nz = plan->n[2], zc = plan->chunk_planes;
+            for (int64_t z0 = 0; z0 < nz; z0 += zc)
+                for (size_t k = i; k < i + 2; ++k)
+                    if (!launch_pass(plan, k, in, out, mode, stream, 1, z0, zc)) return WSFFT_ERROR_HIP;
+            ++i;
+            continue;
+        }
+        if (!launch_pass(plan, i, in, out, mode, stream)) return WSFFT_ERROR_HIP;
+    }
+    return WSFFT_SUCCESS;
+}
+
 wsfft_status_t exec_plan(const wsfft_plan_s* plan, const void* in, void* out, int mode, hipStream_t stream) {
     if (plan->passes.empty()) {   // every axis has length 1: the DFT is the identity
         if (in != out &&
@@ -1251,17 +1277,7 @@ wsfft_status_t exec_plan(const wsfft_plan_s* plan, const void* in, void* out, in
             return WSFFT_ERROR_HIP;
         return WSFFT_SUCCESS;
     }
-    size_t first = 0;
-    if (plan->chunk_planes > 0) {   // x and y chunk by chunk (Infinity Cache policy)
-        const int64_t nz = plan->n[2], zc = plan->chunk_planes;
-        for (int64_t z0 = 0; z0 < nz; z0 += zc)
-            for (size_t i = 0; i < 2; ++i)
-                if (!launch_pass(plan, i, in, out, mode, stream, 1, z0, zc)) return WSFFT_ERROR_HIP;
-        first = 2;
-    }
-    for (size_t i = first; i < plan->passes.size(); ++i)
-        if (!launch_pass(plan, i, in, out, mode, stream)) return WSFFT_ERROR_HIP;
-    return WSFFT_SUCCESS;
+    return run_passes(plan, plan->passes.size(), plan->chunk_at, in, out, mode, stream);
 }
 
 }  // namespace
@@ -1499,6 +1515,17 @@ const PassKernel* find_pass_kernel(StorageKind kind, int sign, int n, bool strid
             return sign < 0 ? find_pass_bf16_neg(n, strided, four_step, v) : find_pass_bf16_pos(n, strided, four_step, v);
         case kF16Math:
             return sign < 0 ? find_pass_f16m_neg(n, strided, four_step, v) : find_pass_f16m_pos(n, strided, four_step, v);
+    }
+    return nullptr;
+}
+
+const PassKernel* find_cached_kernel(StorageKind kind, int sign, int n, bool strided, int fused) {
+    switch (kind) {
+        case kC64: return sign < 0 ? find_cached_c64_neg(n, strided, fused) : find_cached_c64_pos(n, strided, fused);
+        case kF16: return sign < 0 ? find_cached_f16_neg(n, strided, fused) : find_cached_f16_pos(n, strided, fused);
+        case kBF16: return sign < 0 ? find_cached_bf16_neg(n, strided, fused) : find_cached_bf16_pos(n, strided, fused);
+        case kF16Math:
+            return sign < 0 ? find_cached_f16m_neg(n, strided, fused) : find_cached_f16m_pos(n, strided, fused);
     }
     return nullptr;
 }

@@ -76,6 +76,41 @@ def test_cache_policy_bitwise_equal_to_streaming(ws, shape, want, chunk):
 
 
 def test_streaming_flag_only_for_what_it_names(ws):
-    # accepted for 16-bit plans too, where it changes nothing
+    # accepted for every storage type; a 64^3 array takes no cache policy
     p = ws.Plan(64, 64, 64, "fp16", -1, flags=ws.FLAG_STREAMING)
     assert "cached" not in p.describe()
+
+
+# 16-bit storage: cached-store x kernels only, so 512^3 (512 MiB) takes two
+# chunks of 256 planes, and a 128 MiB array (which complex64 would run with
+# cached loads and stores) stays streaming
+@pytest.mark.parametrize("dtype,flags", [("fp16", 0), ("bf16", 0), ("fp16", 4)], ids=["fp16", "bf16", "fp16-math"])
+@pytest.mark.parametrize("shape,want,chunk", [
+    ((512, 512, 512), ("cached-store-contig", "strided", "strided"), 256),
+    ((256, 256, 512), ("contig", "strided", "strided"), 0),
+], ids=["512x512x512", "256x256x512"])
+def test_cache_policy_16bit_bitwise_equal_to_streaming(ws, dtype, flags, shape, want, chunk):
+    nx, ny, nz = shape
+    tdt = torch.float16 if dtype == "fp16" else torch.bfloat16
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12)
+    x = (0.5 * torch.randn((nz, ny, nx, 2), generator=g, device="cuda")).to(tdt)
+    p = ws.Plan(nx, ny, nz, dtype, -1, flags=flags)
+    q = ws.Plan(nx, ny, nz, dtype, -1, flags=flags | ws.FLAG_STREAMING)
+    d = p.describe()
+    print(d)
+    assert labels(d) == want, d
+    assert (f"chunks of {chunk} planes" in d) if chunk else ("chunks" not in d), d
+    for call in ("execute", "execute_inverse"):
+        got = getattr(p, call)(x)
+        ref = getattr(q, call)(x)
+        torch.cuda.synchronize()
+        assert torch.equal(got.view(torch.int16), ref.view(torch.int16)), call
+        del got, ref
+    y1 = x.clone()
+    y2 = x.clone()
+    p.execute(y1, out=y1)
+    q.execute(y2, out=y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.int16), y2.view(torch.int16))
+
