@@ -38,8 +38,8 @@ HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
 # those sources makes the figure stale and it is reported as null.
 KERNEL_SOURCES = ["fft_device.hpp", "pass_config.hpp", "pass_inst.inc", "kernels.hpp", "sizes.inc"]
 MEASURED_TRAFFIC = {     # source hash -> counters of the dominant (z) pass kernel
-    "0b2c6154ac301790": {"kernel": "pencil_pass_kernel<512, 16, 32, true, IoC64, -1, 1, 2, 1>",
-                         "bytes": 2147797675,
+    "699d66b107b60e51": {"kernel": "pencil_pass_kernel<512, 16, 32, true, IoC64, -1, 1, 2, 1>",
+                         "bytes": 2147814101,
                          "profile": "profiles/pencil_pass_512cubed_c64_hbm_counters.md"},
 }
 
@@ -111,6 +111,11 @@ def headline(ws, torch, steps, warmup):
     ms_step, per = time_events(step, steps, warmup)
     wall = time.perf_counter() - t0
     fwd_ms, _ = time_events(lambda: plan.execute(x, y), steps, warmup)
+    # the same step with every pass streaming and no plane chunks (the
+    # library's Infinity Cache policy switched off), for comparison
+    sp = ws.Plan(n, n, n, "c64", -1, ws.FLAG_STREAMING)
+    ms_streaming, _ = time_events(lambda: (sp.execute(x, y), sp.execute_inverse(y, r)), steps, warmup)
+    del sp
     passes = bench_plan_passes(plan, x, y, steps, warmup)
     bytes_per_pass = 2 * N * 8
     for p in passes:
@@ -124,6 +129,7 @@ def headline(ws, torch, steps, warmup):
         "spread_pct": 100.0 * (max(per) - min(per)) / statistics.median(per),
         "us_per_transform": ms_step * 1e3 / 2,
         "us_forward": fwd_ms * 1e3,
+        "us_per_transform_streaming_schedule": ms_streaming * 1e3 / 2,
         "passes": passes,
         "wall_s": wall,
     }
@@ -652,6 +658,8 @@ def main() -> int:
                    "shape": [n, n, n], "storage": "complex64", "transforms_per_step": 2},
         "us_per_transform": us,
         "us_forward": head["us_forward"],
+        "us_per_transform_streaming_schedule": head["us_per_transform_streaming_schedule"],
+        "plan": head["plan"],
         "hbm_frac_3_passes": 3 * algo_bytes / (us * 1e-6) / HBM_PEAK,
         "step_spread_pct": head["spread_pct"],
         "passes": head["passes"],
