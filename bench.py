@@ -189,14 +189,19 @@ def variant_batched(ws, torch, steps, warmup):
     # the same batch with autotuned plans (each pass's launch variant timed at
     # creation; the choices go to this process's tuning cache)
     tuned = [ws.Plan(nx, ny, nz, "c64", -1, ws.FLAG_TUNE) for nx, ny, nz in shapes]
-    ms_tuned, _ = time_events(lambda: ws.execute_batched(tuned, xs, ys), steps, warmup)
+    ms_tuned_pp, _ = time_events(lambda: ws.execute_batched(tuned, xs, ys), steps, warmup)
     n_tuned = sum(d.count(" v1 ") + d.count(" v2 ") for d in (p.describe() for p in tuned))
     del tuned
+    # batch-level tuning: every merged launch of this batch timed in each
+    # launch variant as launched, the fastest recorded (default plans)
+    ws.tune_batched(plans, xs, ys)
+    ms_tuned, _ = time_events(lambda: ws.execute_batched(plans, xs, ys), steps, warmup)
     byts = sum(2 * 8 * nx * ny * nz * sum(d > 1 for d in (nx, ny, nz)) for nx, ny, nz in shapes)
     del xs, ys
     torch.cuda.empty_cache()
     return {"arrays": len(shapes), "elements": tot, "GiB_in_plus_out": 2 * 8 * tot / 2 ** 30,
-            "ms_batched": ms, "ms_batched_tuned": ms_tuned, "tuned_passes_off_default": n_tuned,
+            "ms_batched": ms, "ms_batched_tuned": ms_tuned, "ms_batched_tuned_per_pass": ms_tuned_pp,
+            "tuned_passes_off_default": n_tuned,
             "ms_loop_of_plans": ms_loop, "ms_one_persistent_launch": ms_persist,
             "persistent_tiles": tiles, "persistent_timed_out": timed_out,
             "GFLOPs": fl / (min(ms, ms_persist) * 1e-3) / 1e9,
@@ -236,6 +241,16 @@ def variant_rank(ws, torch, shape, steps, warmup, batch=1, one_launch=False):
                 plan.execute(x, y, stream=s)
         out["ms_graph_replay"], _ = time_events(g.replay, steps, warmup)
         del g
+        # a serving loop captures many transforms into one graph: 20 forward
+        # transforms per replay, reported per transform
+        g20 = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g20, stream=s):
+                for _ in range(20):
+                    plan.execute(x, y, stream=s)
+        ms20, _ = time_events(g20.replay, steps, warmup)
+        out["ms_per_transform_graph_of_20"] = ms20 / 20
+        del g20
     del x, y
     torch.cuda.empty_cache()
     return out

@@ -185,6 +185,24 @@ wsfft_status_t wsfft_execute_inverse(wsfft_plan_t plan, const void* in, void* ou
 wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const void* const* in,
                                      void* const* out, int adjoint, hipStream_t stream);
 
+/*
+ * Batch-level autotuning (paper Section 5.3 runs many small transforms side
+ * by side; here their merged launches are tuned as launched).  Runs the batch
+ * of wsfft_execute_batched with the same arguments, timing every merged
+ * launch (several arrays' pass in one launch) in each compiled launch variant
+ * with HIP events on `stream`, and records the fastest for that launch, keyed
+ * by its kernel shape, storage type, sign and every member's geometry, for
+ * the rest of the process.  Later wsfft_execute_batched calls that produce
+ * the same launch run the recorded variant (otherwise the one most of its
+ * entries' plans chose).  Argument checks as for wsfft_execute_batched.
+ * Synchronises `stream`.  Each launch runs several times, so afterwards
+ * `out` holds unspecified values (and so does `in` where in == out); the
+ * caller's next wsfft_execute_batched computes the transform as usual.
+ * Thread-safe; the records are process-wide.
+ */
+wsfft_status_t wsfft_tune_batched(int count, const wsfft_plan_t* plans, const void* const* in, void* const* out,
+                                  int adjoint, hipStream_t stream);
+
 /* Enqueue only pass `index` (0-based, < wsfft_plan_num_passes) of the
  * transform wsfft_execute (mode 0), wsfft_execute_adjoint (1) or
  * wsfft_execute_inverse (2) would run, with the same buffers.  Running every

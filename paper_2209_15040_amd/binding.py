@@ -70,6 +70,8 @@ _execute_adjoint = _sig("wsfft_execute_adjoint", _int, [_vp, _vp, _vp, _vp])
 _execute_inverse = _sig("wsfft_execute_inverse", _int, [_vp, _vp, _vp, _vp])
 _execute_batched = _sig("wsfft_execute_batched", _int,
                         [_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _int, _vp])
+_tune_batched = _sig("wsfft_tune_batched", _int,
+                     [_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _int, _vp])
 _execute_pass = _sig("wsfft_execute_pass", _int, [_vp, _int, _int, _vp, _vp, _vp])
 _scale_log2 = _sig("wsfft_plan_scale_log2", _int, [_vp])
 _num_passes = _sig("wsfft_plan_num_passes", _int, [_vp])
@@ -222,8 +224,7 @@ class Plan:
             pass
 
 
-def execute_batched(plans, ins, outs, adjoint: bool = False, stream=None) -> None:
-    """``wsfft_execute_batched`` over lists of plans and tensors."""
+def _batch_args(plans, ins, outs):
     n = len(plans)
     if len(ins) != n or len(outs) != n:
         raise ValueError("plans, ins and outs must have one entry each")
@@ -231,10 +232,22 @@ def execute_batched(plans, ins, outs, adjoint: bool = False, stream=None) -> Non
         p._check_tensor(i, "input")
         p._check_tensor(o, "output")
     arr = ctypes.c_void_p * max(n, 1)
-    ph = arr(*[p.handle for p in plans])
-    ip = arr(*[t.data_ptr() for t in ins])
-    op = arr(*[t.data_ptr() for t in outs])
+    return (n, arr(*[p.handle for p in plans]), arr(*[t.data_ptr() for t in ins]),
+            arr(*[t.data_ptr() for t in outs]))
+
+
+def execute_batched(plans, ins, outs, adjoint: bool = False, stream=None) -> None:
+    """``wsfft_execute_batched`` over lists of plans and tensors."""
+    n, ph, ip, op = _batch_args(plans, ins, outs)
     _check(_execute_batched(n, ph, ip, op, int(bool(adjoint)), _stream(stream)), "execute_batched")
+
+
+def tune_batched(plans, ins, outs, adjoint: bool = False, stream=None) -> None:
+    """``wsfft_tune_batched``: time each merged launch of this batch in every
+    launch variant and record the fastest for later ``execute_batched`` calls
+    (synchronises; `outs` hold unspecified values afterwards)."""
+    n, ph, ip, op = _batch_args(plans, ins, outs)
+    _check(_tune_batched(n, ph, ip, op, int(bool(adjoint)), _stream(stream)), "tune_batched")
 
 
 def execute_many(plan: Plan, x: torch.Tensor, out: torch.Tensor, count: int, adjoint: bool = False,

@@ -1157,13 +1157,48 @@ bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out,
     return k->launch(a, nullptr, grid, stream) == hipSuccess;
 }
 
+// Launch variants chosen for whole merged launches by wsfft_tune_batched,
+// keyed by the launch's identity (kernel shape, storage, sign, twiddle
+// precision and every member's geometry).
+std::mutex g_batch_tune_mu;
+std::map<std::string, int> g_batch_tune;
+
+// Microseconds of the best of three runs of three launches of `launch`
+// (after two warm-up launches), or -1 on a launch error.
+template <class F> double time_launches(F&& launch, hipStream_t st) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0;
+    }
+    double best = -1.0;
+    bool ok = launch() && launch();
+    for (int rep = 0; rep < 3 && ok; ++rep) {
+        ok = hipEventRecord(e0, st) == hipSuccess;
+        for (int i = 0; i < 3 && ok; ++i) ok = launch();
+        ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+            const double us = 1000.0 * ms / 3;
+            if (best < 0 || us < best) best = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ok ? best : -1.0;
+}
+
 // Pass `pi` of every entry of a batch.  Direct passes that share a kernel and
 // a twiddle precision go out as merged launches of up to kMaxBatchDescs
-// arrays (one BatchTable each); split-axis passes launch one by one.
+// arrays (one BatchTable each); split-axis passes launch one by one.  With
+// `tune`, every merged launch is first timed in each compiled launch variant
+// (synchronising) and the fastest is recorded for later calls.
 bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const* in, void* const* out,
-                         int mode, size_t pi, hipStream_t stream) {
+                         int mode, size_t pi, hipStream_t stream, bool tune = false) {
     // Entries whose passes differ only in the launch variant the tuner chose
-    // for them alone share one launch: the group runs the variant most of its
+    // for them alone share one launch: the launch runs the variant that
+    // wsfft_tune_batched recorded for it, else the variant most of its
     // entries chose (ties: the lowest), so tuned plans never split a launch
     // that untuned ones would share.
     struct Group {
@@ -1216,9 +1251,31 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
                 if (!launch_pass(plans[i], pi, in[i], out[i], mode, stream)) return false;
                 continue;
             }
+            // this launch's identity, and the variant recorded for it
+            std::string key;
+            {
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "%d:%lld:%lld:%d:%d:%d:%u", g.k0->fused, (long long)g.k0->n,
+                              (long long)g.k0->n2, g.k0->strided ? 1 : 0, (int)g.kind, g.sign, g.twbits);
+                key = buf;
+                for (size_t e = c0; e < c1; ++e) {
+                    const PassArgs& a = plans[g.idx[e]]->passes[pi].args;
+                    std::snprintf(buf, sizeof buf, "|%lld,%lld,%lld,%lld", (long long)a.C, (long long)a.O1,
+                                  (long long)a.es_in, (long long)a.os1_in);
+                    key += buf;
+                }
+            }
+            const PassKernel* k = g.k;
+            if (g.k0->fused == 0) {
+                std::lock_guard<std::mutex> lk(g_batch_tune_mu);
+                auto it = g_batch_tune.find(key);
+                if (it != g_batch_tune.end()) {
+                    const PassKernel* kv = find_pass_kernel(g.kind, g.sign, g.k0->n, g.k0->strided, false, it->second);
+                    if (kv && kv->prepare() == hipSuccess) k = kv;
+                }
+            }
             BatchTable bt{};
             bt.count = (int32_t)(c1 - c0);
-            int64_t tiles = 0;
             PassArgs shared{};
             for (size_t e = c0; e < c1; ++e) {
                 const int i = g.idx[e];
@@ -1236,16 +1293,46 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
                 d.es = P.args.es_in;
                 d.os1 = P.args.os1_in;
                 d.scale = mode == 2 ? P.inv_scale : P.pass_scale;
-                tiles += blocks_for(P, g.k);
-                d.tile_end = tiles;
-                if (e == c0) {
-                    shared = P.args;
-                    // the stage twiddles of the group kernel's radix plan
-                    if (!P.plane) shared.tw = p->tw_dev + P.tw_off + (int64_t)g.k->plan * P.n;
+                d.tile_end = 0;
+                if (e == c0) shared = P.args;
+            }
+            // the tile ranges and stage twiddles of launch kernel kk
+            auto fill = [&](const PassKernel* kk, PassArgs& sa) -> int64_t {
+                int64_t tiles = 0;
+                for (size_t e = c0; e < c1; ++e) {
+                    const wsfft_plan_s* p = plans[g.idx[e]];
+                    const Pass& P = p->passes[pi];
+                    tiles += blocks_for(P, kk);
+                    bt.d[e - c0].tile_end = tiles;
+                    if (e == c0 && !P.plane) sa.tw = p->tw_dev + P.tw_off + (int64_t)kk->plan * P.n;
+                }
+                return tiles;
+            };
+            if (tune && g.k0->fused == 0) {
+                int best_v = -1;
+                double best_us = 0.0;
+                for (int v = 0; v < kMaxVariants; ++v) {
+                    const PassKernel* kv = find_pass_kernel(g.kind, g.sign, g.k0->n, g.k0->strided, false, v);
+                    if (!kv || kv->prepare() != hipSuccess) continue;
+                    PassArgs sa = shared;
+                    const int64_t t = fill(kv, sa);
+                    if (t * kv->threads > 0xffffffffLL) continue;
+                    const double us = time_launches(
+                        [&] { return kv->launch(sa, &bt, dim3((unsigned)t), stream) == hipSuccess; }, stream);
+                    if (us > 0 && (best_v < 0 || us < best_us)) {
+                        best_v = v;
+                        best_us = us;
+                        k = kv;
+                    }
+                }
+                if (best_v >= 0) {
+                    std::lock_guard<std::mutex> lk(g_batch_tune_mu);
+                    g_batch_tune[key] = best_v;
                 }
             }
-            if (tiles * g.k->threads > 0xffffffffLL) return false;
-            if (g.k->launch(shared, &bt, dim3((unsigned)tiles), stream) != hipSuccess) return false;
+            const int64_t tiles = fill(k, shared);
+            if (tiles * k->threads > 0xffffffffLL) return false;
+            if (k->launch(shared, &bt, dim3((unsigned)tiles), stream) != hipSuccess) return false;
         }
     }
     return true;
@@ -1460,8 +1547,8 @@ wsfft_status_t wsfft_execute_c2r_inverse(wsfft_plan_t plan, void* in, float* out
 
 int wsfft_plan_is_real(wsfft_plan_t plan) { return plan_live(plan) ? (plan->real ? 1 : 0) : -1; }
 
-wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const void* const* in,
-                                     void* const* out, int adjoint, hipStream_t stream) {
+static wsfft_status_t batched(int count, const wsfft_plan_t* plans, const void* const* in, void* const* out,
+                              int adjoint, hipStream_t stream, bool tune) {
     if (count < 0) return WSFFT_ERROR_INVALID_VALUE;
     if (count == 0) return WSFFT_SUCCESS;
     if (!plans || !in || !out) return WSFFT_ERROR_NULL_POINTER;
@@ -1497,8 +1584,20 @@ wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const
             if (st != WSFFT_SUCCESS) return st;
         }
     for (size_t pi = 0; pi < maxp; ++pi)
-        if (!launch_level_merged(count, plans, in, out, mode, pi, stream)) return WSFFT_ERROR_HIP;
+        if (!launch_level_merged(count, plans, in, out, mode, pi, stream, tune)) return WSFFT_ERROR_HIP;
     return WSFFT_SUCCESS;
+}
+
+wsfft_status_t wsfft_execute_batched(int count, const wsfft_plan_t* plans, const void* const* in,
+                                     void* const* out, int adjoint, hipStream_t stream) {
+    return batched(count, plans, in, out, adjoint, stream, false);
+}
+
+wsfft_status_t wsfft_tune_batched(int count, const wsfft_plan_t* plans, const void* const* in, void* const* out,
+                                  int adjoint, hipStream_t stream) {
+    const wsfft_status_t st = batched(count, plans, in, out, adjoint, stream, true);
+    if (st != WSFFT_SUCCESS || count == 0) return st;
+    return hipStreamSynchronize(stream) == hipSuccess ? WSFFT_SUCCESS : WSFFT_ERROR_HIP;
 }
 
 }  // extern "C"

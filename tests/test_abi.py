@@ -128,6 +128,16 @@ def test_execute_batched_argument_checks(lib):
     assert f(1, plans, arr, arr, 0, None) == BADPLAN
 
 
+def test_tune_batched_argument_checks(lib):
+    f = lib.wsfft_tune_batched
+    f.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    assert f(-1, None, None, None, 0, None) == INVALID
+    assert f(2, None, None, None, 0, None) == NULLPTR
+    arr = (ctypes.c_void_p * 1)(0x1000)
+    plans = (ctypes.c_void_p * 1)(None)
+    assert f(1, plans, arr, arr, 0, None) == BADPLAN
+
+
 def test_pointwise_argument_checks(lib):
     assert lib.wsfft_real_to_complex(0x1000, 0x2000, -1, None) == INVALID
     assert lib.wsfft_real_to_complex(None, 0x2000, 0, None) == OK

@@ -34,6 +34,29 @@ def test_96_uneven_arrays(ws):
     assert worst <= TOL
 
 
+def test_tune_batched_then_execute(ws):
+    """Batch-level tuning times each merged launch in every launch variant and
+    records the fastest; the following batched calls run the recorded variants
+    and still match the oracle, in both directions."""
+    shapes = [(64, 128, 32), (64, 128, 32), (128, 64, 64), (128, 64, 64), (256, 32, 64), (256, 32, 64),
+              (64, 256, 128), (64, 256, 128)]
+    arrays = [synth.uniform_c((nz, ny, nx), seed=40 + i) for i, (nx, ny, nz) in enumerate(shapes)]
+    plans = [ws.Plan(nx, ny, nz, "c64", -1, ws.FLAG_NO_PLANE) for nx, ny, nz in shapes]
+    xs = [to_dev(a) for a in arrays]
+    ys = [torch.empty_like(x) for x in xs]
+    ws.tune_batched(plans, xs, ys)
+    ws.tune_batched(plans, xs, ys, adjoint=True)
+    for adjoint in (False, True):
+        ws.execute_batched(plans, xs, ys, adjoint=adjoint)
+        torch.cuda.synchronize()
+        for a, y in zip(arrays, ys):
+            want = oracle.fftn(a.astype(np.complex64).astype(np.complex128), +1 if adjoint else -1)
+            assert rel_l2(y.cpu().numpy(), want) <= TOL
+    # inputs are left alone (in != out)
+    for a, x in zip(arrays, xs):
+        assert np.array_equal(to_host(x), a.astype(np.complex64))
+
+
 def test_batched_adjoint_matches_single_calls(ws):
     shapes = [(32, 64, 96), (96, 32, 32), (128, 32, 64), (64, 96, 32)]
     plans = [ws.Plan(*s, "c64", -1) for s in shapes]
