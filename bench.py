@@ -183,6 +183,21 @@ def variant_batched(ws, torch, steps, warmup):
     ms_loop, _ = time_events(lambda: [p.execute(a, b) for p, a, b in zip(plans, xs, ys)], steps, warmup)
     bp = ws.BatchPlan(plans, xs, ys)
     ms_persist, _ = time_events(bp.execute, steps, warmup)
+    # both forms captured into a HIP graph and replayed
+    s = torch.cuda.Stream()
+    graphs = {}
+    with torch.cuda.stream(s):
+        for name, fn in (("merged", lambda: ws.execute_batched(plans, xs, ys, stream=s)),
+                         ("persistent", lambda: bp.execute(stream=s))):
+            fn()
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                fn()
+            graphs[name] = g
+    ms_graph, _ = time_events(graphs["merged"].replay, steps, warmup)
+    ms_persist_graph, _ = time_events(graphs["persistent"].replay, steps, warmup)
+    del graphs
     timed_out = bp.timed_out()
     tiles = bp.tiles
     bp.close()
@@ -203,6 +218,7 @@ def variant_batched(ws, torch, steps, warmup):
             "ms_batched": ms, "ms_batched_tuned": ms_tuned, "ms_batched_tuned_per_pass": ms_tuned_pp,
             "tuned_passes_off_default": n_tuned,
             "ms_loop_of_plans": ms_loop, "ms_one_persistent_launch": ms_persist,
+            "ms_batched_graph_replay": ms_graph, "ms_one_persistent_launch_graph_replay": ms_persist_graph,
             "persistent_tiles": tiles, "persistent_timed_out": timed_out,
             "GFLOPs": fl / (min(ms, ms_persist) * 1e-3) / 1e9,
             "hbm_frac": byts / (min(ms, ms_persist) * 1e-3) / HBM_PEAK}
