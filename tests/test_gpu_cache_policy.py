@@ -114,3 +114,19 @@ def test_cache_policy_16bit_bitwise_equal_to_streaming(ws, dtype, flags, shape, 
     torch.cuda.synchronize()
     assert torch.equal(y1.view(torch.int16), y2.view(torch.int16))
 
+
+
+def test_batched_plans_with_cache_policy_match_single_calls(ws):
+    """Plans of either policy mode inside wsfft_execute_batched (their cached
+    kernels in merged launches; a chunked plan's passes over whole arrays)
+    give the same bits as each plan's own call."""
+    shapes = [(256, 256, 256), (512, 512, 96), (512, 512, 512), (64, 64, 64)]
+    plans = [ws.Plan(nx, ny, nz, "c64", -1) for nx, ny, nz in shapes]
+    xs = [torch.from_numpy(synth.normal_c64((nz, ny, nx), seed=20 + i)).cuda() for i, (nx, ny, nz) in enumerate(shapes)]
+    ys = [torch.empty_like(x) for x in xs]
+    for adjoint in (False, True):
+        ws.execute_batched(plans, xs, ys, adjoint=adjoint)
+        for p, x, y in zip(plans, xs, ys):
+            ref = p.execute_adjoint(x) if adjoint else p.execute(x)
+            torch.cuda.synchronize()
+            assert torch.equal(torch.view_as_real(y), torch.view_as_real(ref)), (p.describe(), adjoint)
