@@ -79,8 +79,10 @@ __device__ __forceinline__ void run_type(int type, const PassArgs& a, int64_t t,
     }
 }
 
-__device__ __forceinline__ unsigned load_acquire(const unsigned* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// A coherent (agent-scope) load of a counter without ordering: an acquire
+// load would invalidate the caches at every poll.
+__device__ __forceinline__ unsigned load_relaxed(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Control flow is kept wave-uniform: wave 0 claims (lane 0 issues the atomics,
@@ -128,16 +130,26 @@ __global__ __launch_bounds__(kPT, 2) void persist_kernel(const PersistPass* __re
         const int L = pi < 0 ? kPersistMaxLevels : __builtin_amdgcn_readfirstlane(passes[pi].level);
         if (L != level) {
             if (pending != 0) {   // publish the finished tiles of `level`
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                // Each wave waits for its own stores to reach the L2; then one
+                // agent-scope release by wave 0 writes the XCD's L2 back for
+                // the whole workgroup (the write-back is cache-wide, and the
+                // barrier orders the other waves' stores before it), and the
+                // count goes out after it.  A release per wave would repeat
+                // the cache-wide write-back four times.
+                __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
-                if (lane0) __hip_atomic_fetch_add(&ctr->done[level], pending, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (wave0) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    if (lane0)
+                        __hip_atomic_fetch_add(&ctr->done[level], pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
                 pending = 0;
             }
             if (L > 0 && L < kPersistMaxLevels) {   // bounded wait for the whole previous level
                 if (wave0) {
                     const unsigned need = (unsigned)(lv.end[L - 1] - (L >= 2 ? lv.end[L - 2] : 0));
                     for (unsigned spins = 0;; ++spins) {
-                        const unsigned have = __builtin_amdgcn_readfirstlane(load_acquire(&ctr->done[L - 1]));
+                        const unsigned have = __builtin_amdgcn_readfirstlane(load_relaxed(&ctr->done[L - 1]));
                         if (have >= need) break;
                         // give up after spin_limit polls, or at once after
                         // another workgroup has given up
@@ -150,9 +162,14 @@ __global__ __launch_bounds__(kPT, 2) void persist_kernel(const PersistPass* __re
                         }
                         __builtin_amdgcn_s_sleep(2);
                     }
+                    // the polls read the counter without ordering; one acquire
+                    // after the last invalidates this CU's L1 and the XCD's L2
+                    // for the whole workgroup, and the barrier orders the other
+                    // waves' loads after it (an acquire per wave would repeat
+                    // the cache-wide invalidation)
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 __syncthreads();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the previous level
             }
             level = L;
         }
@@ -176,8 +193,11 @@ __global__ __launch_bounds__(kPT, 2) void persist_kernel(const PersistPass* __re
     }
     // last workgroup out resets the counters for the next launch
     if (lane0) {
-        const unsigned prevf = __hip_atomic_fetch_add(&ctr->finished, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // release: this workgroup's counter updates come before its count;
+        // only the last workgroup out needs the acquire
+        const unsigned prevf = __hip_atomic_fetch_add(&ctr->finished, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (prevf + 1 == gridDim.x) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             for (int i = 0; i < kPersistMaxLevels; ++i) ctr->done[i] = 0;
             ctr->ticket = 0;
             if (__hip_atomic_load(&ctr->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
