@@ -193,9 +193,12 @@ __global__ __launch_bounds__(kPT, 2) void persist_kernel(const PersistPass* __re
     }
     // last workgroup out resets the counters for the next launch
     if (lane0) {
-        // release: this workgroup's counter updates come before its count;
-        // only the last workgroup out needs the acquire
-        const unsigned prevf = __hip_atomic_fetch_add(&ctr->finished, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // The tiles were written back at the last publication; waiting for
+        // this lane's counter atomics to complete puts them before its count
+        // (without a cache-wide write-back per workgroup).  Only the last
+        // workgroup out needs the acquire.
+        __builtin_amdgcn_s_waitcnt(0);
+        const unsigned prevf = __hip_atomic_fetch_add(&ctr->finished, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prevf + 1 == gridDim.x) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             for (int i = 0; i < kPersistMaxLevels; ++i) ctr->done[i] = 0;
