@@ -319,6 +319,14 @@ def variant_real(ws, torch, steps, warmup):
     for i in range(plan.num_passes):
         pm, _ = time_events(lambda i=i: plan.execute_pass(i, x, H, 0), steps, warmup)
         passes.append(pm)
+    # the same with half-spectrum rows padded to whole cache lines (272
+    # complex values: 17 lines of 128 bytes)
+    pp = ws.RealPlan(n, n, n, pitch=272)
+    Hp = torch.empty((n, n, 272), dtype=torch.complex64, device="cuda")
+    ms_p, _ = time_events(lambda: (pp.r2c(x, Hp), pp.c2r(Hp, r, inverse=True)), steps, warmup)
+    fwd_p, _ = time_events(lambda: pp.r2c(x, Hp), steps, warmup)
+    plan_p = pp.describe()
+    del pp, Hp
     half = (n // 2 + 1) * n * n
     # bytes per R2C: x pass reads N FP32 and writes the half spectrum; y and z
     # read and write the half spectrum; the C2R mirrors it
@@ -330,6 +338,8 @@ def variant_real(ws, torch, steps, warmup):
             "GFLOPs_c2c_equivalent": flops(N) / (us * 1e-6) / 1e9,
             "bytes_per_transform": byts, "bytes_c2c_transform": 6 * N * 8,
             "hbm_frac": byts / (us * 1e-6) / HBM_PEAK, "r2c_pass_ms": passes,
+            "us_per_transform_padded_rows": ms_p * 1e3 / 2, "us_r2c_padded_rows": fwd_p * 1e3,
+            "plan_padded_rows": plan_p,
             "note": "GFLOP/s counts the complex 5 N log2 N of the same grid, as a real transform's "
                     "equivalent rate"}
 

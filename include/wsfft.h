@@ -281,8 +281,22 @@ void wsfft_batch_plan_destroy(wsfft_batch_plan_t batch);
  * WSFFT_ERROR_INVALID_VALUE for a real plan, and the real calls for a complex
  * plan.  Enqueue only, like every execute call.
  * wsfft_plan_is_real: 1 for a real plan, 0 for a complex one, -1 invalid.
+ *
+ * wsfft_plan_create_real_ex: the same with half-spectrum rows `half_pitch`
+ * complex values apart (0: nx/2 + 1, the compact layout above; otherwise at
+ * least nx/2 + 1, else WSFFT_ERROR_INVALID_VALUE): element (kx, y, z) of the
+ * half spectrum sits at kx + half_pitch*(y + ny*z), a tensor of shape (nz,
+ * ny, half_pitch) of which [..., :nx/2+1] is the spectrum.  Compact rows of
+ * nx/2 + 1 complex64 are not whole 128-byte cache lines apart, so passes
+ * that stream across rows share lines between tiles; a pitch that is a
+ * multiple of 16 makes every row line-aligned, and the plan's y and z
+ * passes then stream whole rows.  Those passes transform the padding columns
+ * along with the spectrum, so the padding positions hold unspecified values
+ * after a call (they never reach the result).  The Poisson solve
+ * (wsfft_pointwise.h) takes compact real plans only.
  */
 wsfft_plan_t wsfft_plan_create_real(int64_t nx, int64_t ny, int64_t nz, unsigned flags);
+wsfft_plan_t wsfft_plan_create_real_ex(int64_t nx, int64_t ny, int64_t nz, unsigned flags, int64_t half_pitch);
 wsfft_status_t wsfft_execute_r2c(wsfft_plan_t plan, const float* in, void* out, hipStream_t stream);
 wsfft_status_t wsfft_execute_c2r(wsfft_plan_t plan, void* in, float* out, hipStream_t stream);
 wsfft_status_t wsfft_execute_c2r_inverse(wsfft_plan_t plan, void* in, float* out, hipStream_t stream);

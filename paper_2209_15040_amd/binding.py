@@ -92,6 +92,7 @@ _poisson_symbol = _sig("wsfft_poisson_symbol", _int, [_vp, _i64, _i64, _i64, _vp
 _poisson_solve = _sig("wsfft_poisson_solve", _int, [_vp, _vp, _vp, _vp, _vp])
 _poisson_solve_noalloc = _sig("wsfft_poisson_solve_noalloc", _int, [_vp, _vp, _vp, _vp])
 _plan_create_real = _sig("wsfft_plan_create_real", _vp, [_i64, _i64, _i64, ctypes.c_uint])
+_plan_create_real_ex = _sig("wsfft_plan_create_real_ex", _vp, [_i64, _i64, _i64, ctypes.c_uint, _i64])
 _execute_r2c = _sig("wsfft_execute_r2c", _int, [_vp, _vp, _vp, _vp])
 _execute_c2r = _sig("wsfft_execute_c2r", _int, [_vp, _vp, _vp, _vp])
 _execute_c2r_inverse = _sig("wsfft_execute_c2r_inverse", _int, [_vp, _vp, _vp, _vp])
@@ -329,15 +330,22 @@ class RealPlan:
     ``r2c(x)``: float32 (nz, ny, nx) -> complex64 half spectrum, forward sign,
     unnormalised.  ``c2r(X)``: half spectrum -> float32, sign +1, unnormalised
     (``inverse=True``: times 1/N, the inverse of ``r2c``); the C2R transform
-    overwrites its input."""
+    overwrites its input.  ``pitch`` (``wsfft_plan_create_real_ex``): half
+    spectrum rows of ``pitch`` complex values, shape (nz, ny, pitch), of which
+    [..., :nx/2 + 1] is the spectrum (a multiple of 16 aligns every row to
+    cache lines); 0 is the compact layout."""
 
-    def __init__(self, nx: int, ny: int = 1, nz: int = 1, flags: int = 0):
+    def __init__(self, nx: int, ny: int = 1, nz: int = 1, flags: int = 0, pitch: int = 0):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.nxh = self.nx // 2 + 1
+        self.pitch = int(pitch) if pitch else self.nxh
         self.device = torch.cuda.current_device()
-        h = _plan_create_real(self.nx, self.ny, self.nz, int(flags))
+        if pitch:
+            h = _plan_create_real_ex(self.nx, self.ny, self.nz, int(flags), int(pitch))
+        else:
+            h = _plan_create_real(self.nx, self.ny, self.nz, int(flags))
         if not h:
-            raise WsfftError(_get_last_error(), f"plan_create_real({nx},{ny},{nz})")
+            raise WsfftError(_get_last_error(), f"plan_create_real({nx},{ny},{nz}, pitch={pitch})")
         self._h = h
 
     @property
@@ -350,7 +358,7 @@ class RealPlan:
 
     @property
     def half_size(self) -> int:
-        return self.nxh * self.ny * self.nz
+        return self.pitch * self.ny * self.nz
 
     @property
     def num_passes(self) -> int:
@@ -361,7 +369,7 @@ class RealPlan:
         return _work_bytes(self._h)
 
     def half_shape(self, real_shape) -> tuple:
-        return tuple(real_shape[:-1]) + (self.nxh,)
+        return tuple(real_shape[:-1]) + (self.pitch,)
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(4096)

@@ -182,6 +182,20 @@ def test_plan_create_real_rejects(lib, dims, flags, want):
     assert lib.wsfft_get_last_error() == want
 
 
+@pytest.mark.parametrize("dims,pitch,want", [
+    ((8, 8, 8), 4, INVALID),            # pitch below nx/2 + 1
+    ((8, 8, 8), -1, INVALID),
+    ((8, 8, 8), 2 ** 21, INVALID),
+    ((9, 8, 8), 16, UNSUPPORTED),       # odd real axis
+])
+def test_plan_create_real_ex_rejects(lib, dims, pitch, want):
+    f = lib.wsfft_plan_create_real_ex
+    f.restype = ctypes.c_void_p
+    f.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_uint, ctypes.c_int64]
+    assert f(*dims, 0, pitch) is None
+    assert lib.wsfft_get_last_error() == want
+
+
 def test_real_calls_reject_invalid_plans(lib):
     bogus = ctypes.c_void_p(0x1000)
     for name in ("wsfft_execute_r2c", "wsfft_execute_c2r", "wsfft_execute_c2r_inverse"):

@@ -116,3 +116,57 @@ def test_rfftn_irfftn_functions(ws):
     back = ws.irfftn(H, 24)
     assert torch.equal(H, Hc), "irfftn modified its input"
     assert rel_l2(to_host(back), a) <= TOL_RT
+
+
+# Padded half spectrum (wsfft_plan_create_real_ex): rows `pitch` complex
+# values apart.  The padded plan runs the same arithmetic as the compact one
+# on every spectrum column (aligned rows only change the cache policy of its
+# passes, and its y and z passes also transform the padding columns), so the
+# spectrum part is compared bitwise with the compact plan's, and C2R from
+# padded input with C2R from compact input.
+PADDED = [((8, 6, 512), 272), ((32, 32, 32), 32), ((32, 32, 32), 20), ((1, 1, 32768), 16400),
+          ((4, 2048, 16), 16), ((3, 18, 64), 48), ((2, 3, 4), 8)]
+
+
+@pytest.mark.parametrize("shape,pitch", PADDED, ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else str(v))
+def test_padded_half_spectrum_matches_compact(ws, shape, pitch):
+    nz, ny, nx = shape
+    nxh = nx // 2 + 1
+    a = real_input(shape, seed=5 + nx + ny + nz)
+    x = torch.from_numpy(a).cuda()
+    pc = ws.RealPlan(nx, ny, nz)
+    pp = ws.RealPlan(nx, ny, nz, pitch=pitch)
+    print(pp.describe())
+    Hc = pc.r2c(x)
+    Hp = torch.view_as_complex(torch.full((nz, ny, pitch, 2), float("nan"), device="cuda"))
+    pp.r2c(x, out=Hp)
+    torch.cuda.synchronize()
+    # NaN in the padding (transformed along by the y and z passes) must not
+    # reach the spectrum
+    assert torch.equal(torch.view_as_real(Hp[..., :nxh]), torch.view_as_real(Hc))
+    for inverse in (False, True):
+        Hp2 = torch.zeros((nz, ny, pitch), dtype=torch.complex64, device="cuda")
+        Hp2[..., :nxh] = Hc
+        got = pp.c2r(Hp2, inverse=inverse)
+        want = pc.c2r(Hc.clone(), inverse=inverse)
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), inverse
+    rt = to_host(pp.c2r(Hp, inverse=True))
+    assert rel_l2(rt, a) <= TOL_RT
+
+
+def test_padded_plan_against_oracle(ws):
+    nz, ny, nx = 16, 24, 96
+    a = real_input((nz, ny, nx), seed=77)
+    p = ws.RealPlan(nx, ny, nz, pitch=64)
+    H = p.r2c(torch.from_numpy(a).cuda())
+    assert rel_l2(to_host(H)[..., :nx // 2 + 1], oracle.rfftn(a.astype(np.float64))) <= TOL
+
+
+def test_poisson_solve_rejects_padded_real_plans(ws):
+    p = ws.RealPlan(32, 32, 32, pitch=32)
+    f = torch.zeros((32, 32, 32), device="cuda")
+    u = torch.empty_like(f)
+    w = torch.empty((32, 32, 32), dtype=torch.complex64, device="cuda")
+    st = ws._poisson_solve(p.handle, f.data_ptr(), u.data_ptr(), w.data_ptr(), None)
+    assert st == 1   # WSFFT_ERROR_INVALID_VALUE
