@@ -12,8 +12,13 @@
 // writes the outputs back in place.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "kernels.hpp"
 #include "pass_config.hpp"
+#include "plane.hpp"
 
 namespace wsfft {
 namespace {
@@ -122,10 +127,15 @@ struct PlaneXY {
     // The first x stage reads the plane from HBM and the last y stage writes
     // it back, so LDS holds the plane only between stages.
     __device__ __forceinline__ static void run_plane(const PassArgs& a, int64_t t, float2* lds) {
-        const char* src = reinterpret_cast<const char*>(static_cast<const float2*>(a.src) + t * a.os1_in);
-        char* dst = reinterpret_cast<char*>(static_cast<float2*>(a.dst) + t * a.os1_out);
-        transform<NX, NY, LX, 1, true, true, false>(lds, a.tw, src, nullptr, 1.0f);    // rows: pencils along x
-        transform<NY, NX, 1, LX, false, false, true>(lds, a.tw4, nullptr, dst, a.scale);   // columns: along y
+        run(a.src, a.dst, a.tw, a.tw4, a.os1_in, a.os1_out, a.scale, t, lds);
+    }
+    __device__ __forceinline__ static void run(const void* src0, void* dst0, const float2* tw, const float2* tw4,
+                                               int64_t stride_in, int64_t stride_out, float scale, int64_t t,
+                                               float2* lds) {
+        const char* src = reinterpret_cast<const char*>(static_cast<const float2*>(src0) + t * stride_in);
+        char* dst = reinterpret_cast<char*>(static_cast<float2*>(dst0) + t * stride_out);
+        transform<NX, NY, LX, 1, true, true, false>(lds, tw, src, nullptr, 1.0f);    // rows: pencils along x
+        transform<NY, NX, 1, LX, false, false, true>(lds, tw4, nullptr, dst, scale);   // columns: along y
     }
 };
 
@@ -178,12 +188,119 @@ hipError_t plane_prepare() {
 const PassKernel kPlaneNeg[] = {WSFFT_PLANES(WSFFT_PLANE_NEG)};
 const PassKernel kPlanePos[] = {WSFFT_PLANES(WSFFT_PLANE_POS)};
 
+// Plane passes of several shapes in one launch.  A merged batch level would
+// otherwise launch once per plane shape, and most of those launches are too
+// small to fill the chip (a few hundred planes, some microseconds each, the
+// start-up and the last partial wave of workgroups costing as much as the
+// transform); one launch per class keeps the chip full from one shape's
+// planes to the next.  A class groups the shapes that share a workgroup size
+// and an LDS bracket, so a class launch keeps the residency of its shapes'
+// own launches.
+struct PlaneShape {
+    int nx, ny;
+};
+#define WSFFT_PLANE_SHAPE(NX, NY) {NX, NY},
+constexpr PlaneShape kPlaneShapes[] = {WSFFT_PLANES(WSFFT_PLANE_SHAPE)};
+constexpr int kNumPlaneShapes = (int)(sizeof(kPlaneShapes) / sizeof(kPlaneShapes[0]));
+// below 4096 values: 256 threads, at most 28 KB of LDS; 4096 .. 6144: 512
+// threads, at most 53 KB; 8192: 512 threads, at most 74 KB
+constexpr int class_of(int values) { return values < 4096 ? 0 : (values <= 6144 ? 1 : 2); }
+constexpr int class_threads(int cls) { return cls == 0 ? 256 : 512; }
+constexpr int shape_lds(int nx, int ny) { return ny * (nx + 4) * (int)sizeof(float2); }
+constexpr int class_lds(int cls) {
+    int m = 0;
+    for (const PlaneShape& p : kPlaneShapes)
+        if (class_of(p.nx * p.ny) == cls && shape_lds(p.nx, p.ny) > m) m = shape_lds(p.nx, p.ny);
+    return m;
+}
+static_assert(kPlaneClasses == 3, "three plane classes");
+
+template <int CLS, int SIGN, int S = 0>
+__device__ __forceinline__ void run_shape(const PlaneEntry& e, int64_t t, float2* lds) {
+    if constexpr (S < kNumPlaneShapes) {
+        constexpr int NX = kPlaneShapes[S].nx, NY = kPlaneShapes[S].ny;
+        if constexpr (class_of(NX * NY) == CLS) {
+            static_assert(plane_threads(NX * NY) == class_threads(CLS), "a class shares one workgroup size");
+            static_assert(PlaneXY<NX, NY, SIGN>::lds_bytes() == shape_lds(NX, NY), "LDS of a plane shape");
+            if (e.shape == S) {
+                PlaneXY<NX, NY, SIGN>::run(e.src, e.dst, e.tw, e.tw4, e.stride, e.stride, e.scale, t, lds);
+                return;
+            }
+        }
+        run_shape<CLS, SIGN, S + 1>(e, t, lds);
+    }
+}
+
+template <int CLS, int SIGN>
+__global__ __launch_bounds__(class_threads(CLS)) void plane_class_kernel(PlaneTable pt) {
+    extern __shared__ float2 lds_dyn[];
+    const int64_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < pt.count && b >= pt.e[i].plane_end) ++i;
+    run_shape<CLS, SIGN>(pt.e[i], b - (i ? pt.e[i - 1].plane_end : 0), lds_dyn);
+}
+
+template <int CLS, int SIGN>
+hipError_t class_launch(const PlaneTable& t, unsigned planes, int lds, hipStream_t s) {
+    hipLaunchKernelGGL((plane_class_kernel<CLS, SIGN>), dim3(planes), dim3(class_threads(CLS)), lds, s, t);
+    return hipGetLastError();
+}
+
+template <int CLS, int SIGN>
+hipError_t class_prepare() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&plane_class_kernel<CLS, SIGN>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, class_lds(CLS));
+}
+
+using ClassLaunch = hipError_t (*)(const PlaneTable&, unsigned, int, hipStream_t);
+using ClassPrepare = hipError_t (*)();
+const ClassLaunch kClassLaunch[2][kPlaneClasses] = {
+    {&class_launch<0, -1>, &class_launch<1, -1>, &class_launch<2, -1>},
+    {&class_launch<0, 1>, &class_launch<1, 1>, &class_launch<2, 1>}};
+const ClassPrepare kClassPrepare[2][kPlaneClasses] = {
+    {&class_prepare<0, -1>, &class_prepare<1, -1>, &class_prepare<2, -1>},
+    {&class_prepare<0, 1>, &class_prepare<1, 1>, &class_prepare<2, 1>}};
+
 }  // namespace
 
 const PassKernel* find_plane_kernel(int nx, int ny, int sign) {
     for (const PassKernel& k : (sign < 0 ? kPlaneNeg : kPlanePos))
         if (k.n == nx && k.n2 == ny) return &k;
     return nullptr;
+}
+
+bool plane_shape_info(int nx, int ny, int* cls, int* shape, int* lds_bytes) {
+    for (int i = 0; i < kNumPlaneShapes; ++i)
+        if (kPlaneShapes[i].nx == nx && kPlaneShapes[i].ny == ny) {
+            *cls = class_of(nx * ny);
+            *shape = i;
+            *lds_bytes = shape_lds(nx, ny);
+            return true;
+        }
+    return false;
+}
+
+hipError_t plane_class_prepare(int cls, int sign) {
+    if (cls < 0 || cls >= kPlaneClasses) return hipErrorInvalidValue;
+    // once per kernel and device
+    static std::mutex mu;
+    static std::set<std::pair<int, int>> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const int key = (sign < 0 ? 0 : kPlaneClasses) + cls;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count({dev, key})) return hipSuccess;
+    e = kClassPrepare[sign < 0 ? 0 : 1][cls]();
+    if (e == hipSuccess) done.insert({dev, key});
+    return e;
+}
+
+hipError_t plane_class_launch(int cls, int sign, const PlaneTable& t, unsigned planes, int lds, hipStream_t s) {
+    if (cls < 0 || cls >= kPlaneClasses || t.count < 1 || t.count > kMaxPlaneEntries || lds > class_lds(cls) ||
+        planes != (unsigned)t.e[t.count - 1].plane_end)
+        return hipErrorInvalidValue;
+    return kClassLaunch[sign < 0 ? 0 : 1][cls](t, planes, lds, s);
 }
 
 }  // namespace wsfft

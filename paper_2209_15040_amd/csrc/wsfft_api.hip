@@ -25,6 +25,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <string>
 #include <unordered_set>
@@ -35,6 +36,7 @@
 #include "kernels.hpp"
 #include "pass_config.hpp"
 #include "persist.hpp"
+#include "plane.hpp"
 
 using namespace wsfft;
 
@@ -1179,6 +1181,20 @@ bool launch_pass(const wsfft_plan_s* plan, size_t pi, const void* in, void* out,
     return k->launch(a, nullptr, grid, stream) == hipSuccess;
 }
 
+// A kernel's function attributes (its dynamic LDS limit), set once per kernel
+// and device: the batched paths look kernels up on every call.
+bool prepared(const PassKernel* k) {
+    static std::mutex mu;
+    static std::set<std::pair<int, const PassKernel*>> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count({dev, k})) return true;
+    if (k->prepare() != hipSuccess) return false;
+    done.insert({dev, k});
+    return true;
+}
+
 // Launch variants chosen for whole merged launches by wsfft_tune_batched,
 // keyed by the launch's identity (kernel shape, storage, sign, twiddle
 // precision and every member's geometry).
@@ -1233,14 +1249,9 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
         const PassKernel* k;           // the kernel the group runs
     };
     std::vector<Group> groups;
-    for (int i = 0; i < count; ++i) {
+    auto add_to_group = [&](int i) {
         const wsfft_plan_s* p = plans[i];
-        if (pi >= p->passes.size()) continue;
         const Pass& P = p->passes[pi];
-        if (P.four_step != 0) {
-            if (!launch_pass(p, pi, in[i], out[i], mode, stream)) return false;
-            continue;
-        }
         const int sign = mode == 0 ? p->sign : -p->sign;
         const PassKernel* k = sign < 0 ? P.kern_neg : P.kern_pos;
         const StorageKind kind = kind_of(p->dtype, p->flags);
@@ -1256,14 +1267,80 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
         }
         if (k->variant >= 0 && k->variant < kMaxVariants) ++g->votes[k->variant];
         g->idx.push_back(i);
+    };
+    // plane passes by sign and plane class: a class that holds more than one
+    // plane shape in this level goes out as mixed-shape launches
+    std::vector<int> plane_bucket[2][kPlaneClasses];
+    for (int i = 0; i < count; ++i) {
+        const wsfft_plan_s* p = plans[i];
+        if (pi >= p->passes.size()) continue;
+        const Pass& P = p->passes[pi];
+        if (P.four_step != 0) {
+            if (!launch_pass(p, pi, in[i], out[i], mode, stream)) return false;
+            continue;
+        }
+        int cls, shape, lds;
+        if (P.plane && P.args.os1_in == P.args.os1_out && plane_shape_info((int)P.n, (int)P.n2, &cls, &shape, &lds)) {
+            const int sign = mode == 0 ? p->sign : -p->sign;
+            plane_bucket[sign < 0 ? 0 : 1][cls].push_back(i);
+            continue;
+        }
+        add_to_group(i);
     }
+    for (int sg = 0; sg < 2; ++sg)
+        for (int cls = 0; cls < kPlaneClasses; ++cls) {
+            const std::vector<int>& b = plane_bucket[sg][cls];
+            bool mixed = false;
+            for (int i : b) {
+                const Pass& P0 = plans[b[0]]->passes[pi];
+                const Pass& P = plans[i]->passes[pi];
+                mixed = mixed || P.n != P0.n || P.n2 != P0.n2;
+            }
+            if (!mixed) {
+                for (int i : b) add_to_group(i);
+                continue;
+            }
+            if (plane_class_prepare(cls, sg == 0 ? -1 : 1) != hipSuccess) return false;
+            for (size_t c0 = 0; c0 < b.size(); c0 += kMaxPlaneEntries) {
+                const size_t c1 = std::min(b.size(), c0 + (size_t)kMaxPlaneEntries);
+                PlaneTable t{};
+                t.count = (int32_t)(c1 - c0);
+                int64_t planes = 0;
+                int lds_max = 0;
+                for (size_t e = c0; e < c1; ++e) {
+                    const int i = b[e];
+                    const wsfft_plan_s* p = plans[i];
+                    const Pass& P = p->passes[pi];
+                    const bool ip = in[i] == out[i];
+                    auto sel = [&](int s) -> void* {
+                        return s == 0 ? const_cast<void*>(in[i]) : (s == 1 ? out[i] : p->work);
+                    };
+                    int c, shape, lds;
+                    (void)plane_shape_info((int)P.n, (int)P.n2, &c, &shape, &lds);
+                    PlaneEntry& d = t.e[e - c0];
+                    d.src = sel(ip ? P.src_sel_ip : P.src_sel);
+                    d.dst = sel(ip ? P.dst_sel_ip : P.dst_sel);
+                    d.tw = P.args.tw;
+                    d.tw4 = P.args.tw4;
+                    d.stride = P.args.os1_in;
+                    d.scale = mode == 2 ? P.inv_scale : P.pass_scale;
+                    d.shape = shape;
+                    planes += P.args.C;
+                    d.plane_end = planes;
+                    lds_max = std::max(lds_max, lds);
+                }
+                if (planes < 1 || planes > 0x7fffffffLL) return false;
+                if (plane_class_launch(cls, sg == 0 ? -1 : 1, t, (unsigned)planes, lds_max, stream) != hipSuccess)
+                    return false;
+            }
+        }
     for (Group& g : groups) {
         if (g.k0->fused != 0) continue;   // fused kernels have no variants
         int best = 0;
         for (int v = 1; v < kMaxVariants; ++v)
             if (g.votes[v] > g.votes[best]) best = v;
         const PassKernel* k = find_pass_kernel(g.kind, g.sign, g.k0->n, g.k0->strided, false, best);
-        if (k && k->prepare() == hipSuccess) g.k = k;
+        if (k && prepared(k)) g.k = k;
     }
     for (const Group& g : groups) {
         for (size_t c0 = 0; c0 < g.idx.size(); c0 += kMaxBatchDescs) {
@@ -1293,7 +1370,7 @@ bool launch_level_merged(int count, const wsfft_plan_t* plans, const void* const
                 auto it = g_batch_tune.find(key);
                 if (it != g_batch_tune.end()) {
                     const PassKernel* kv = find_pass_kernel(g.kind, g.sign, g.k0->n, g.k0->strided, false, it->second);
-                    if (kv && kv->prepare() == hipSuccess) k = kv;
+                    if (kv && prepared(kv)) k = kv;
                 }
             }
             BatchTable bt{};

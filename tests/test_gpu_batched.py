@@ -69,6 +69,38 @@ def test_batched_adjoint_matches_single_calls(ws):
         assert torch.equal(single, y)
 
 
+PLANE_SHAPES = [(32, 32), (32, 64), (64, 32), (32, 96), (96, 32), (32, 128), (128, 32), (32, 256), (256, 32),
+                (64, 64), (64, 96), (96, 64), (64, 128), (128, 64)]
+
+
+@pytest.mark.parametrize("adjoint", [False, True], ids=["forward", "adjoint"])
+@pytest.mark.parametrize("in_place", [False, True], ids=["out-of-place", "in-place"])
+def test_mixed_plane_shapes_match_single_calls(ws, adjoint, in_place):
+    """Every fused plane shape in one batch, 35 arrays of the 8192-value
+    shapes among them (more than one mixed-shape launch holds), plus arrays
+    without a plane pass: each result equals the array's own plan call
+    bitwise, and the oracle for a few."""
+    shapes = [(nx, ny, 1 + i % 3) for i, (nx, ny) in enumerate(PLANE_SHAPES)]
+    big = [(32, 256), (256, 32), (64, 128), (128, 64)]
+    shapes += [(*big[i % 4], 1 + i % 2) for i in range(35)]
+    shapes += [(512, 8, 3), (16, 16, 4), (4096, 1, 1)]
+    plans = [ws.Plan(nx, ny, nz, "c64", -1) for nx, ny, nz in shapes]
+    arrays = [synth.uniform_c((nz, ny, nx), seed=300 + i).astype(np.complex64) for i, (nx, ny, nz) in enumerate(shapes)]
+    xs = [to_dev(a) for a in arrays]
+    ys = xs if in_place else [torch.empty_like(x) for x in xs]
+    singles = []
+    for p, a in zip(plans, arrays):
+        x1 = to_dev(a)
+        singles.append(p.execute_adjoint(x1) if adjoint else p.execute(x1))
+    ws.execute_batched(plans, xs, ys, adjoint=adjoint)
+    torch.cuda.synchronize()
+    for i, (y, single) in enumerate(zip(ys, singles)):
+        assert torch.equal(y, single), f"entry {i} shape {shapes[i]}"
+    for i in (0, 8, 13, 20, len(shapes) - 3):
+        want = oracle.fftn(arrays[i].astype(np.complex128), +1 if adjoint else -1)
+        assert rel_l2(to_host(ys[i]), want) <= TOL
+
+
 def test_uniform_batch_is_one_array_per_entry(ws):
     """Same plan, buffers one array apart: the single-launch path."""
     n, count = 4096, 64
