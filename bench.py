@@ -63,6 +63,15 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+# Untimed warm-up of the variants beyond their warm-up calls, in milliseconds
+# of wall time with the GPU busy: after an idle period (each variant first
+# generates its inputs on the host) the GPU needs about 30 ms of work to reach
+# its steady clocks (512^3 FP16: 700 us per transform in the first ten, ~612
+# from the thirtieth on).  The headline keeps exactly its W warm-up steps.
+VARIANT_WARM_MS = 50.0
+_warm_ms = 0.0
+
+
 def time_events(fn, steps: int, warmup: int):
     """Per-call milliseconds of fn() over `steps` calls, HIP events on the
     current stream (the stream the library launches on)."""
@@ -70,6 +79,11 @@ def time_events(fn, steps: int, warmup: int):
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if _warm_ms > 0:
+        t0 = time.perf_counter()
+        while (time.perf_counter() - t0) * 1e3 < _warm_ms:
+            fn()
+            torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record()
     for i in range(steps):
@@ -658,6 +672,8 @@ def main() -> int:
                 "traffic_source": meas["profile"] if meas else "no counters recorded for these kernel sources"}
     variants = {}
     if not args.no_variants:
+        global _warm_ms
+        _warm_ms = VARIANT_WARM_MS
         vs = max(5, K // 2)
         runs = {
             "fp16": lambda: variant_c16(ws, torch, "fp16", vs, 2),
