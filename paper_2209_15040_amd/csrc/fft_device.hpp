@@ -23,6 +23,8 @@
 // four multiplies and two adds of a complex product into FMAC operations).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
@@ -620,6 +622,8 @@ struct PassArgs {
     int32_t tw4_mode;     // 0: none; 1: output e of column c times W_M^(c*e), table entry c*N + e;
                           // 2: times W_M^(o1*e), table entry o1*e
     int32_t tstore;       // strided layout only: store columns as contiguous runs via LDS
+    int32_t tw4_shift;    // complex64 mode 1 with tstore: tw4 holds two FP64 tables instead,
+                          // W_M^j for j < 2^tw4_shift, then W_M^(j * 2^tw4_shift)
     float scale;          // multiplies every stored value
     int32_t sym_nx;       // kFlagPoisson / kFlagSolveZ: column c of the z pass is
     int32_t sym_ny;       //   (x, y) = (c mod sym_nx, c div sym_nx)
@@ -907,7 +911,33 @@ struct PencilPass {
     // output position, entry g*N + e, so lanes with consecutive e read
     // consecutive entries; mode 2 (g = o1, the same for the whole tile) reads
     // the plain table W_M^m at m = g*e.
+    // Complex64 pass A of a unit-stride split axis (tw4_mode 1) takes its
+    // twiddles from two small FP64 tables instead of one entry per output:
+    // W_M^m = W_M^(m mod 2^s) * W_M^(2^s * (m div 2^s)), rounded once to FP32.
+    // With the transposed store each thread keeps one element over columns D
+    // apart (TW_RECUR), so the products run as an FP64 recurrence.
+    static constexpr bool TW64 = FOURSTEP && STRIDED && std::is_same<IO, IoC64>::value;
+    static constexpr bool TW_RECUR = TW64 && (T * P) % ROWS == 0;
+    // W_M^m (m < M) from the two FP64 tables at a.tw4 (tw4_shift)
+    __device__ __forceinline__ static double2 root64(const PassArgs& a, uint32_t m) {
+        const double2* lo = reinterpret_cast<const double2*>(a.tw4);
+        const double2 p = lo[m & ((1u << a.tw4_shift) - 1u)];
+        const double2 q = lo[(1u << a.tw4_shift) + (m >> a.tw4_shift)];
+        return make_double2(p.x * q.x - p.y * q.y, p.x * q.y + p.y * q.x);
+    }
+    // W_M^m with the pass's sign, rounded once to FP32 (complex64 only)
+    __device__ __forceinline__ static V tw64_of(const PassArgs& a, uint32_t m) {
+        if constexpr (TW64) {
+            const double2 w = root64(a, m);
+            return make_float2((float)w.x, SIGN > 0 ? -(float)w.y : (float)w.y);
+        } else {
+            return cconst<V>(1.0, 0.0);   // never called: only complex64 passes hold FP64 tables
+        }
+    }
     __device__ __forceinline__ static V tw4_of(int e, int64_t col, int64_t o1, const PassArgs& a) {
+        if constexpr (TW64) {
+            if (a.tw4_mode == 1) return tw64_of(a, (uint32_t)col * (uint32_t)e);
+        }
         const uint32_t m = a.tw4_mode == 1 ? (uint32_t)col * N + e : (uint32_t)o1 * e;   // < M <= 2^20
         const f32x2 wv = *gload_at<f32x2>(reinterpret_cast<const char*>(a.tw4), m * 8u);
         V w = cvt_value<V>(wv);
@@ -1100,14 +1130,45 @@ struct PencilPass {
                 // twiddles are all requested before the first use
                 constexpr int PER = (ROWS * P + T * P - 1) / (T * P);
                 V w4[PER];
-                if (FOURSTEP && a.tw4_mode != 0) {
+                bool tw_done = false;
+                if constexpr (TW_RECUR) {
+                    if (a.tw4_mode == 1) {
+                        tw_done = true;
+                        // complex64: the thread's element e is the same in all its
+                        // columns, which are D apart, so W_M^((c0 + pl) * e) runs
+                        // as an FP64 recurrence from W_M^((c0 + pl0) * e) with step
+                        // W_M^(D * e), rounded once to FP32 per use (reading one
+                        // table entry per output made such a pass 14% slower)
+                        constexpr int D = T * P / ROWS;
+                        const uint32_t pl0 = threadIdx.x / ROWS;
+                        const uint64_t e = threadIdx.x % ROWS + (uint64_t)h * ROWS, M = (uint64_t)a.M;
+                        uint64_t x0 = (uint64_t)(c0 + pl0) * e, xs = (uint64_t)D * e;
+                        if (x0 >= M) x0 %= M;
+                        if (xs >= M) xs %= M;
+                        double2 w = root64(a, (uint32_t)x0);
+                        const double2 st = root64(a, (uint32_t)xs);
+#pragma unroll
+                        for (int i = 0; i < PER; ++i) {
+                            const int pl = (int)pl0 + i * D;
+                            if (pl < P && c0 + pl < a.C) {
+                                w4[i] = make_float2((float)w.x, SIGN > 0 ? -(float)w.y : (float)w.y);
+                            } else {
+                                w4[i] = cconst<V>(1.0, 0.0);
+                            }
+                            w = make_double2(w.x * st.x - w.y * st.y, w.x * st.y + w.y * st.x);
+                        }
+                    }
+                }
+                if (!tw_done && FOURSTEP && a.tw4_mode != 0) {
 #pragma unroll
                     for (int i = 0; i < PER; ++i) {
                         const int idx = threadIdx.x + i * T * P;
                         const int pl = idx / ROWS, el = idx % ROWS;
                         const uint32_t e = (uint32_t)(el + h * ROWS);
                         const uint32_t m = a.tw4_mode == 1 ? (uint32_t)pl * N + e : o1w * e;
-                        if (idx < ROWS * P && c0 + pl < a.C) {
+                        if (TW64 && a.tw4_mode == 1 && idx < ROWS * P && c0 + pl < a.C) {
+                            w4[i] = tw64_of(a, (uint32_t)(c0 + pl) * e);
+                        } else if (idx < ROWS * P && c0 + pl < a.C) {
                             const f32x2 wv = *gload_at<f32x2>(twbase, m * 8u);
                             w4[i] = cvt_value<V>(wv);
                             if (SIGN > 0) w4[i].y = -w4[i].y;

@@ -327,8 +327,19 @@ void log_plan(const std::string& desc) {
 //          split axis, so lanes that store consecutive outputs read
 //          consecutive entries;
 //  kHalf: entry m is W_len^m for m = 0 .. len/4, the recombination twiddles
-//          of the half-spectrum passes of a real axis of len points.
-enum { kStage = 0, kPlain = 1, kMatrix = 2, kHalf = 3 };
+//          of the half-spectrum passes of a real axis of len points;
+//  kPair64: two FP64 tables (each entry two slots, 16-byte aligned),
+//          W_len^j for j < 2^s and then W_len^(j * 2^s) for j < ceil(len / 2^s),
+//          s = pair64_shift(len): the inter-pass twiddles of pass A of a
+//          unit-stride split axis of complex64 plans, which the kernel
+//          multiplies out in FP64 and rounds once.
+enum { kStage = 0, kPlain = 1, kMatrix = 2, kHalf = 3, kPair64 = 4 };
+// the smallest s with 2^s >= sqrt(len): both tables hold about sqrt(len) entries
+int pair64_shift(int64_t len) {
+    int s = 0;
+    while ((int64_t(1) << (2 * s)) < len) ++s;
+    return s;
+}
 struct TableSet {
     struct Table { int kind; int64_t len, n1, off; };
     std::vector<Table> tables;
@@ -336,8 +347,14 @@ struct TableSet {
     int64_t get(int kind, int64_t len, int64_t n1 = 0) {
         for (auto& t : tables)
             if (t.kind == kind && t.len == len && t.n1 == n1) return t.off;
+        if (kind == kPair64 && total % 2 != 0) ++total;   // 16-byte alignment
         tables.push_back({kind, len, n1, total});
-        total += kind == kStage ? kTwPlans * len : (kind == kHalf ? len / 4 + 1 : len);
+        if (kind == kPair64) {
+            const int64_t L = int64_t(1) << pair64_shift(len);
+            total += 2 * (L + (len + L - 1) / L);
+        } else {
+            total += kind == kStage ? kTwPlans * len : (kind == kHalf ? len / 4 + 1 : len);
+        }
         return tables.back().off;
     }
 };
@@ -367,6 +384,16 @@ wsfft_status_t upload_tables(const TableSet& ts, int mant, int emin, float2** de
             }
         } else if (t.kind == kHalf) {
             for (int64_t m = 0; m <= t.len / 4; ++m) put(t.off + m, m, t.len);
+        } else if (t.kind == kPair64) {
+            // FP64 entries, not rounded to the storage format
+            const int64_t L = int64_t(1) << pair64_shift(t.len), H = (t.len + L - 1) / L;
+            auto put64 = [&](int64_t slot, int64_t m) {
+                double v[2];
+                root_fp64(m % t.len, t.len, &v[0], &v[1]);
+                std::memcpy(&host[(size_t)(t.off + 2 * slot)], v, sizeof v);
+            };
+            for (int64_t j = 0; j < L; ++j) put64(j, j);
+            for (int64_t j = 0; j < H; ++j) put64(L + j, j * L);
         } else {
             for (int64_t m = 0; m < t.len; ++m) put(t.off + m, t.n1 > 0 ? (m / t.n1) * (m % t.n1) : m, t.len);
         }
@@ -754,7 +781,12 @@ static wsfft_plan_t plan_create(int64_t nx, int64_t ny, int64_t nz, int dt, int 
             A.n = n1; B.n = n2;
             A.four_step = 1; B.four_step = 2;
             A.tw_off = table_for(kStage, n1); B.tw_off = table_for(kStage, n2);
-            A.tw4_off = A.args.tw4_mode == 1 ? table_for(kMatrix, g.n, n1) : table_for(kPlain, g.n);
+            if (A.args.tw4_mode == 1 && kind == kC64) {
+                A.tw4_off = table_for(kPair64, g.n);
+                A.args.tw4_shift = pair64_shift(g.n);
+            } else {
+                A.tw4_off = A.args.tw4_mode == 1 ? table_for(kMatrix, g.n, n1) : table_for(kPlain, g.n);
+            }
             B.tw4_off = -1;
             // the axis scale 2^-sp is split between the two passes
             const int sa = sp / 2, sb = sp - sa;
