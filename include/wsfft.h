@@ -22,8 +22,11 @@
  * Arithmetic is FP32 (the paper measures FP32 and FP16; Section 4.1 and
  * Section 5), or packed FP16 for WSFFT_C16_FP16 plans created with
  * WSFFT_FLAG_FP16_MATH.  Twiddle factors are evaluated in FP64 on the host and rounded
- * to nearest even: to the storage type for the 16-bit types, to FP32 for
- * WSFFT_C64 or when WSFFT_FLAG_FP32_TWIDDLES is given.
+ * once to nearest even: to the storage type for the 16-bit types, to FP32 for
+ * WSFFT_C64 or when WSFFT_FLAG_FP32_TWIDDLES is given.  (The inter-pass
+ * twiddles of a WSFFT_C64 unit-stride axis split in two passes are FP64
+ * products of two such host tables, formed on the device and rounded once to
+ * FP32.)
  *
  * Reduced precision: each pass p of a 16-bit plan multiplies its output by
  * 2^-s_p with s_p = ceil(log2(n_p) / 2), so the stored result is
