@@ -104,7 +104,7 @@ typedef enum {
  * FP16 whatever WSFFT_FLAG_FP32_TWIDDLES says. */
 #define WSFFT_FLAG_FP16_MATH 4u
 /* WSFFT_C64 plans whose x and y axes each take one pass and whose xy-plane
- * holds at most 8192 values (axes of 32 .. 256 points) fuse the x and y
+ * holds at most 16384 values (axes of 32 .. 256 points) fuse the x and y
  * supersteps into one pass over whole planes in LDS (two HBM round trips
  * for a 3D array instead of three).  This flag keeps them separate. */
 #define WSFFT_FLAG_NO_PLANE 8u

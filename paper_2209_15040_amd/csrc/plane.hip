@@ -1,7 +1,7 @@
 // The x and y supersteps of an array whose xy-plane fits in LDS, fused into
 // one pass.  Supersteps may be grouped freely (paper, Section 1: the 1D
 // transforms along each axis can be taken in any order); a workgroup loads a
-// whole plane (nx * ny contiguous complex64 values, at most 64 KiB), runs
+// whole plane (nx * ny contiguous complex64 values, at most 128 KiB), runs
 // every x transform and then every y transform of it in LDS, and stores it,
 // so the array makes two HBM round trips (plane, then z) instead of three.
 //
@@ -23,16 +23,17 @@
 namespace wsfft {
 namespace {
 
-// threads per workgroup: 512 for planes of 4096 values or more, else 256
-// (a 32 x 32 plane gives 256 threads one butterfly each per stage)
-constexpr int plane_threads(int values) { return values >= 4096 ? 512 : 256; }
+// threads per workgroup: 1024 for planes above 8192 values (one such
+// workgroup per CU: its LDS holds the whole plane), 512 for 4096 .. 8192,
+// else 256 (a 32 x 32 plane gives 256 threads one butterfly each per stage)
+constexpr int plane_threads(int values) { return values > 8192 ? 1024 : (values >= 4096 ? 512 : 256); }
 constexpr int kPlaneRadixPlan = 1;   // stage twiddle block of radix plan 1 (radix <= 16)
 
 template <int NX, int NY, int SIGN>
 struct PlaneXY {
     static constexpr int E = NX * NY;
     static constexpr int kPlaneThreads = plane_threads(E);
-    static_assert(E * 8 <= 64 * 1024, "a plane holds at most 8192 values");
+    static_assert(E * 8 <= 128 * 1024, "a plane holds at most 16384 values");
     // LDS row pitch: 4 values (32 bytes) of padding per row, so the threads
     // of an x stage, which take 8 to 16 consecutive butterflies of each of
     // several rows, spread over all banks (rows NX * 8 bytes apart would all
@@ -173,11 +174,15 @@ hipError_t plane_prepare() {
 }
 
 // (nx, ny) pairs with a fused plane pass: the axis lengths of the uneven
-// batch workload (32 .. 256) whose plane holds at most 8192 values, so two
-// workgroups fit per CU.
+// batch workload (32 .. 256) whose plane holds at most 16384 values (planes
+// of up to 8192 values let two workgroups share a CU; the larger ones take
+// one, and still beat the two passes they replace: 96 x 96 x 128 17 against
+// 20 us, 128 x 128 x 256 31 against 42 us; 128 x 128 x 64, 21 against 18 us,
+// is the exception among the batch's shapes)
 #define WSFFT_PLANES(X)                                                                             \
     X(32, 32) X(32, 64) X(64, 32) X(32, 96) X(96, 32) X(32, 128) X(128, 32) X(32, 256) X(256, 32) \
-    X(64, 64) X(64, 96) X(96, 64) X(64, 128) X(128, 64)
+    X(64, 64) X(64, 96) X(96, 64) X(64, 128) X(128, 64)                                           \
+    X(96, 96) X(128, 96) X(96, 128) X(128, 128) X(64, 256) X(256, 64)
 
 #define WSFFT_PLANE_ENTRY(NX, NY, SIGN)                                                                        \
     {NX, false, false, 0, plane_threads(NX * NY), 1, PlaneXY<NX, NY, SIGN>::lds_bytes(), kPlaneRadixPlan,     \
@@ -203,9 +208,10 @@ struct PlaneShape {
 constexpr PlaneShape kPlaneShapes[] = {WSFFT_PLANES(WSFFT_PLANE_SHAPE)};
 constexpr int kNumPlaneShapes = (int)(sizeof(kPlaneShapes) / sizeof(kPlaneShapes[0]));
 // below 4096 values: 256 threads, at most 28 KB of LDS; 4096 .. 6144: 512
-// threads, at most 53 KB; 8192: 512 threads, at most 74 KB
-constexpr int class_of(int values) { return values < 4096 ? 0 : (values <= 6144 ? 1 : 2); }
-constexpr int class_threads(int cls) { return cls == 0 ? 256 : 512; }
+// threads, at most 53 KB; 8192: 512 threads, at most 74 KB; 9216 .. 16384:
+// 1024 threads, at most 136 KB
+constexpr int class_of(int values) { return values < 4096 ? 0 : (values <= 6144 ? 1 : (values <= 8192 ? 2 : 3)); }
+constexpr int class_threads(int cls) { return cls == 0 ? 256 : (cls == 3 ? 1024 : 512); }
 constexpr int shape_lds(int nx, int ny) { return ny * (nx + 4) * (int)sizeof(float2); }
 constexpr int class_lds(int cls) {
     int m = 0;
@@ -213,7 +219,7 @@ constexpr int class_lds(int cls) {
         if (class_of(p.nx * p.ny) == cls && shape_lds(p.nx, p.ny) > m) m = shape_lds(p.nx, p.ny);
     return m;
 }
-static_assert(kPlaneClasses == 3, "three plane classes");
+static_assert(kPlaneClasses == 4, "four plane classes");
 
 template <int CLS, int SIGN, int S = 0>
 __device__ __forceinline__ void run_shape(const PlaneEntry& e, int64_t t, float2* lds) {
@@ -255,11 +261,11 @@ hipError_t class_prepare() {
 using ClassLaunch = hipError_t (*)(const PlaneTable&, unsigned, int, hipStream_t);
 using ClassPrepare = hipError_t (*)();
 const ClassLaunch kClassLaunch[2][kPlaneClasses] = {
-    {&class_launch<0, -1>, &class_launch<1, -1>, &class_launch<2, -1>},
-    {&class_launch<0, 1>, &class_launch<1, 1>, &class_launch<2, 1>}};
+    {&class_launch<0, -1>, &class_launch<1, -1>, &class_launch<2, -1>, &class_launch<3, -1>},
+    {&class_launch<0, 1>, &class_launch<1, 1>, &class_launch<2, 1>, &class_launch<3, 1>}};
 const ClassPrepare kClassPrepare[2][kPlaneClasses] = {
-    {&class_prepare<0, -1>, &class_prepare<1, -1>, &class_prepare<2, -1>},
-    {&class_prepare<0, 1>, &class_prepare<1, 1>, &class_prepare<2, 1>}};
+    {&class_prepare<0, -1>, &class_prepare<1, -1>, &class_prepare<2, -1>, &class_prepare<3, -1>},
+    {&class_prepare<0, 1>, &class_prepare<1, 1>, &class_prepare<2, 1>, &class_prepare<3, 1>}};
 
 }  // namespace
 

@@ -32,7 +32,7 @@ struct PlaneTable {
 // Plane shapes with a plane pass share a launch when they share a class
 // (workgroup size and LDS bracket).  Returns false when (nx, ny) has no plane
 // pass; else its class (0 .. kPlaneClasses-1), shape index and LDS bytes.
-constexpr int kPlaneClasses = 3;
+constexpr int kPlaneClasses = 4;
 bool plane_shape_info(int nx, int ny, int* cls, int* shape, int* lds_bytes);
 // Sets the class kernel's dynamic LDS limit (once per class and sign).
 hipError_t plane_class_prepare(int cls, int sign);

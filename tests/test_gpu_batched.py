@@ -70,16 +70,18 @@ def test_batched_adjoint_matches_single_calls(ws):
 
 
 PLANE_SHAPES = [(32, 32), (32, 64), (64, 32), (32, 96), (96, 32), (32, 128), (128, 32), (32, 256), (256, 32),
-                (64, 64), (64, 96), (96, 64), (64, 128), (128, 64)]
+                (64, 64), (64, 96), (96, 64), (64, 128), (128, 64),
+                (96, 96), (128, 96), (96, 128), (128, 128), (64, 256), (256, 64)]
 
 
 @pytest.mark.parametrize("adjoint", [False, True], ids=["forward", "adjoint"])
 @pytest.mark.parametrize("in_place", [False, True], ids=["out-of-place", "in-place"])
 def test_mixed_plane_shapes_match_single_calls(ws, adjoint, in_place):
-    """Every fused plane shape in one batch, 35 arrays of the 8192-value
-    shapes among them (more than one mixed-shape launch holds), plus arrays
-    without a plane pass: each result equals the array's own plan call
-    bitwise, and the oracle for a few."""
+    """Every fused plane shape in one batch (the 9216- to 16384-value ones in
+    1024-thread workgroups), 35 arrays of the 8192-value shapes among them
+    (more than one mixed-shape launch holds), plus arrays without a plane
+    pass: each result equals the array's own plan call bitwise, and the
+    oracle for a few."""
     shapes = [(nx, ny, 1 + i % 3) for i, (nx, ny) in enumerate(PLANE_SHAPES)]
     big = [(32, 256), (256, 32), (64, 128), (128, 64)]
     shapes += [(*big[i % 4], 1 + i % 2) for i in range(35)]
@@ -96,7 +98,7 @@ def test_mixed_plane_shapes_match_single_calls(ws, adjoint, in_place):
     torch.cuda.synchronize()
     for i, (y, single) in enumerate(zip(ys, singles)):
         assert torch.equal(y, single), f"entry {i} shape {shapes[i]}"
-    for i in (0, 8, 13, 20, len(shapes) - 3):
+    for i in (0, 8, 13, 14, 17, 19, 20, len(shapes) - 3):
         want = oracle.fftn(arrays[i].astype(np.complex128), +1 if adjoint else -1)
         assert rel_l2(to_host(ys[i]), want) <= TOL
 
